@@ -1,0 +1,158 @@
+"""Plain FP64 sketches, adjoints and matrix-free kernel gradients.
+
+Test infrastructure only (see ``oracle/__init__.py``).
+
+Everything here is the plain definition written out with an explicit operator R
+from ``oracle.operators`` and a dense product (a library matmul serves as the
+product step).  Section 1 states the two sketches used by HSS construction:
+S = A R for the column space and, for nonsymmetric A, S' = A^* R for the row
+space (A is real in this build, so A^* = A^T).
+"""
+import numpy as np
+
+from . import operators as ops
+
+
+def sketch(A, R):
+    """S = A R in FP64."""
+    return np.asarray(A, dtype=np.float64) @ np.asarray(R, dtype=np.float64)
+
+
+def sketch_t(A, R):
+    """S' = A^T R in FP64."""
+    return np.asarray(A, dtype=np.float64).T @ np.asarray(R, dtype=np.float64)
+
+
+def sketch_columns(A, kind, n, widths, seed, cols, alpha=4, transpose=False):
+    """Selected columns of S (or S') without forming all of R.
+
+    ``cols`` are global column indices of R.  For each one the column of R is
+    formed from the element formulas and S(:, j) = sum_k A(:, k) R(k, j).
+    """
+    A = np.asarray(A)
+    offs = np.cumsum([0] + list(widths))
+    out = np.zeros((A.shape[1] if transpose else A.shape[0], len(cols)))
+    for t, j in enumerate(cols):
+        b = int(np.searchsorted(offs, j, side="right") - 1)
+        Rb = ops.operator_block(kind, n, widths[b], b, int(offs[b]), seed, alpha)
+        r = Rb[:, j - offs[b]]
+        nz = np.nonzero(r)[0]
+        if transpose:
+            out[:, t] = A[nz, :].astype(np.float64).T @ r[nz]
+        else:
+            out[:, t] = A[:, nz].astype(np.float64) @ r[nz]
+    return out
+
+
+def adjoint(dS, R):
+    """dA = dS R^T: the adjoint of A -> A R applied to dS (FP64)."""
+    return np.asarray(dS, dtype=np.float64) @ np.asarray(R, dtype=np.float64).T
+
+
+# ------------------------------------------------------------- matrix-free kernel
+def kernel_matrix(X, Y, h, shift=0.0):
+    """K_ij = exp(-|x_i - y_j|^2 / (2 h^2)) in FP64, plus shift on the diagonal
+    when X and Y are the same point set."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    d2 = ((X[:, None, :] - Y[None, :, :]) ** 2).sum(-1)
+    K = np.exp(-d2 / (2.0 * h * h))
+    if shift and X.shape == Y.shape and np.array_equal(X, Y):
+        K = K + shift * np.eye(X.shape[0])
+    return K
+
+
+def kernel_sketch(X, h, R, shift=0.0, block_rows=2048):
+    """S = K(X, h) R without storing K: row blocks of K are formed one at a time."""
+    X = np.asarray(X, dtype=np.float64)
+    N = X.shape[0]
+    S = np.zeros((N, R.shape[1]))
+    for i0 in range(0, N, block_rows):
+        i1 = min(N, i0 + block_rows)
+        d2 = ((X[i0:i1, None, :] - X[None, :, :]) ** 2).sum(-1)
+        Kb = np.exp(-d2 / (2.0 * h * h))
+        S[i0:i1] = Kb @ R
+        if shift:
+            S[i0:i1] += shift * R[i0:i1]
+    return S
+
+
+def kernel_loss(X, h, R, W, shift=0.0):
+    """L = sum(W o S) with S = K(X, h) R."""
+    return float(np.sum(np.asarray(W, np.float64) * kernel_sketch(X, h, R, shift)))
+
+
+def kernel_grad(X, h, R, W, block_rows=1024):
+    """Closed-form gradient of L = sum(W o (K R)) with respect to X and h.
+
+    With G = W R^T (dL/dK) and K_ij = exp(-r_ij^2 / (2h^2)):
+      dK_ij/dx_i = -K_ij (x_i - x_j) / h^2,   dK_ij/dx_j = +K_ij (x_i - x_j) / h^2,
+      dK_ij/dh   =  K_ij r_ij^2 / h^3,
+    so dL/dx_i = -(1/h^2) sum_j (G_ij + G_ji) K_ij (x_i - x_j) (K is symmetric) and
+    dL/dh = sum_ij G_ij K_ij r_ij^2 / h^3.  The diagonal shift does not depend on
+    X or h and drops out.  Returns (dX, dh) in FP64.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    N = X.shape[0]
+    dX = np.zeros_like(X)
+    dh = 0.0
+    for i0 in range(0, N, block_rows):
+        i1 = min(N, i0 + block_rows)
+        diff = X[i0:i1, None, :] - X[None, :, :]           # (b, N, dim)
+        d2 = (diff ** 2).sum(-1)
+        K = np.exp(-d2 / (2.0 * h * h))
+        G = W[i0:i1] @ R.T                                   # G_ij for rows i0..i1
+        Gt = R[i0:i1] @ W.T                                  # G_ji = (W R^T)_ji
+        M = (G + Gt) * K
+        dX[i0:i1] = -(M[:, :, None] * diff).sum(1) / (h * h)
+        dh += float((G * K * d2).sum()) / h ** 3
+    return dX, dh
+
+
+def finite_difference_grad(X, h, R, W, coords, step=1e-4):
+    """Central finite differences of L = sum(W o (K(X,h) R)) in FP64.
+
+    coords: list of (i, a) coordinates of X; also returns dL/dh.
+    """
+    X = np.asarray(X, dtype=np.float64).copy()
+    out = []
+    for i, a in coords:
+        x0 = X[i, a]
+        X[i, a] = x0 + step
+        lp = kernel_loss(X, h, R, W)
+        X[i, a] = x0 - step
+        lm = kernel_loss(X, h, R, W)
+        X[i, a] = x0
+        out.append((lp - lm) / (2 * step))
+    dh = (kernel_loss(X, h + step, R, W) - kernel_loss(X, h - step, R, W)) / (2 * step)
+    return np.array(out), dh
+
+
+def rel_fro(x, ref):
+    """||x - ref||_F / ||ref||_F in FP64."""
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = np.linalg.norm(ref)
+    return float(np.linalg.norm(x - ref) / (den if den > 0 else 1.0))
+
+
+def frobenius_ratio(A, R):
+    """||A R||_F^2 / ||A||_F^2: the quantity the Frobenius stopping test relies on
+    (section 4, Theorems 4.1-4.4: it concentrates at 1 for JL operators)."""
+    A = np.asarray(A, dtype=np.float64)
+    return float(np.linalg.norm(A @ R) ** 2 / np.linalg.norm(A) ** 2)
+
+
+def split_bf16x3(A):
+    """Split FP32 values a = a1 + a2 + a3 with each part on the bfloat16 grid
+    (round-to-nearest-even at every step).  Returns three FP64 arrays."""
+    a = np.asarray(A, dtype=np.float32).astype(np.float64)
+    a1 = ops.bf16_round(a)
+    r1 = a - a1
+    a2 = ops.bf16_round(r1)
+    r2 = r1 - a2
+    a3 = ops.bf16_round(r2)
+    return a1, a2, a3
+
