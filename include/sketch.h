@@ -1,0 +1,175 @@
+/* sketch.h - C ABI of the MI355X sketching library (libhsketch.so).
+ *
+ * The library computes the randomized sketches used by adaptive HSS
+ * construction (Yaniv, Ghysels, Malik, Boateng, Li, arXiv 2302.01977):
+ *   S  = A R     (section 1: post-multiplication of A by a tall random n x d R)
+ *   S' = A^T R   (section 1: needed for the row space when A is nonsymmetric;
+ *                 A is real here, so A^* = A^T)
+ * where R = [R_0 | R_1 | ...] is a Gaussian, SJLT or SRHT operator (section 2.3),
+ * grown block by block as Algorithm 1 appends JL-Operator(dd, n) columns.
+ *
+ * Conventions for every entry point
+ *   - Return value: SK_OK (0) or a negative status; nothing throws across the ABI.
+ *     sketch_last_error() returns a thread-local message for the last failure.
+ *   - Matrices are column-major with an explicit leading dimension (in elements).
+ *   - "device" pointers are HIP device allocations owned by the caller; the
+ *     library never frees them.  "host" pointers are ordinary host memory.
+ *   - stream is a hipStream_t (NULL = the default stream).  Compute calls only
+ *     enqueue work and return; they do not synchronise the host.  Calls marked
+ *     "synchronises" wait for the stream before returning.
+ *   - Operator entries are a pure function of (seed, block, index): see the
+ *     counter layout in paper_2302_01977_amd/csrc/spec.hpp.  Each block is its
+ *     own JL operator normalised by its own width w_b (Gaussian N(0, 1/w_b),
+ *     SJLT +-1/sqrt(alpha), SRHT +-1/sqrt(w_b)).
+ */
+#ifndef HSKETCH_SKETCH_H
+#define HSKETCH_SKETCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SK_OK 0
+#define SK_EINVAL (-1)       /* bad argument: NULL pointer, ld < rows, width <= 0, alpha does not divide a width, ... */
+#define SK_EUNSUPPORTED (-2) /* valid request this build does not implement (e.g. SRHT with n not a power of two) */
+#define SK_ENOMEM (-3)       /* device or host allocation failed */
+#define SK_EHIP (-4)         /* a HIP runtime call failed; the message carries hipGetErrorString */
+#define SK_ESTATE (-5)       /* released, foreign or corrupted handle/context */
+
+/* operator kinds (section 2.3) */
+#define SK_GAUSSIAN 0 /* i.i.d. N(0, 1/w_b) entries (values on the bfloat16 grid) */
+#define SK_SJLT 1     /* block construction: alpha chunks of w_b/alpha columns, one +-1/sqrt(alpha) per chunk and row */
+#define SK_SRHT 2     /* R = D H P / sqrt(w_b)-scaled; D Rademacher, H Sylvester-Hadamard (natural order), P uniform samples */
+
+/* element types of A and of the sketches */
+#define SK_F64 0
+#define SK_F32 1
+
+/* Gaussian arithmetic (ignored by SJLT and SRHT, which add in the element type) */
+#define SK_PREC_NATIVE 0 /* FP64 A: FP64 matrix cores; FP32 A: FP64 matrix cores on promoted values */
+#define SK_PREC_BF16 1   /* FP32 A rounded to bf16, bf16 matrix cores, FP32 accumulation */
+#define SK_PREC_BF16X3 2 /* FP32 A split exactly into three bf16 parts, three bf16 products, FP32 accumulation */
+
+/* input kinds */
+#define SK_DENSE 0  /* stored matrix A */
+#define SK_POINTS 1 /* matrix-free Gaussian kernel K_ij = exp(-|x_i - x_j|^2 / (2 h^2)) + shift * delta_ij */
+
+typedef struct sk_ctx sk_ctx;       /* per-device state: properties, workspace, tuning table */
+typedef struct sk_handle sk_handle; /* one operator R = [R_0 | R_1 | ...] and its device metadata */
+
+typedef struct {
+  int32_t input;     /* SK_DENSE or SK_POINTS */
+  int32_t dtype;     /* SK_F64 or SK_F32 (SK_POINTS: SK_F32) */
+  int64_t m, n, lda; /* DENSE: A is m x n column-major, lda >= max(1, m) */
+  const void *A;     /* DENSE: device pointer to A */
+  int32_t symmetric; /* DENSE: nonzero = A is symmetric, S' is not formed */
+  int32_t dim;       /* POINTS: coordinates per point, 1..4 */
+  const float *X;    /* POINTS: device pointer, N x dim row-major FP32 */
+  int64_t N;         /* POINTS: number of points; the kernel matrix is N x N */
+  float h;           /* POINTS: bandwidth h > 0 */
+  float shift;       /* POINTS: diagonal shift */
+} sk_input;
+
+typedef struct {
+  int32_t kind;  /* SK_GAUSSIAN, SK_SJLT or SK_SRHT */
+  int32_t alpha; /* SJLT: nonzeros per row, 1..32, must divide every block width */
+  int32_t prec;  /* SK_PREC_* (Gaussian only) */
+  int32_t flags; /* reserved, must be 0 */
+} sk_op_desc;
+
+typedef struct {
+  void *S;      /* device, m x d_new column-major, element type = dtype; never NULL */
+  int64_t ldS;  /* >= m */
+  void *St;     /* device, n x d_new column-major, or NULL: S' not formed */
+  int64_t ldSt; /* >= n when St != NULL */
+} sk_output;
+
+/* sketch_init: create a context on HIP device `device` (section 1: the sketch is
+ * the preprocessing step of the compression).  *ctx receives the new context.
+ * Errors: SK_EINVAL (ctx NULL or device out of range), SK_EHIP. */
+int sketch_init(sk_ctx **ctx, int32_t device);
+
+/* sketch_finalize: destroy a context created by sketch_init; every handle made
+ * from it must have been released.  Synchronises the device.  SK_ESTATE if ctx
+ * is not a live context. */
+int sketch_finalize(sk_ctx *ctx);
+
+/* sketch_last_error: message describing the last failed call on this thread
+ * (empty string if none).  The pointer stays valid until the next call. */
+const char *sketch_last_error(void);
+
+/* sketch_apply: draw block 0 of R (width d) from `seed` and compute
+ *   S = A R  into out->S (m x d), and, if out->St != NULL, S' = A^T R into out->St
+ *   (n x d; requires m == n and a nonsymmetric input)           -- section 1, eq. S <- A R
+ * For SK_POINTS, S = K(X, h) R with K generated on the fly (N x N never stored).
+ * *h receives a new handle owning the operator metadata (release with
+ * sketch_release).  d > 0; SJLT needs alpha | d; the SJLT and SRHT kernels need
+ * d % 16 == 0; SRHT needs n a power of two.  Asynchronous on `stream`.
+ * Errors: SK_EINVAL, SK_EUNSUPPORTED, SK_ENOMEM, SK_EHIP. */
+int sketch_apply(sk_ctx *ctx, const sk_input *in, const sk_op_desc *op, int32_t d, uint64_t seed,
+                 const sk_output *out, sk_handle **h, void *stream);
+
+/* sketch_extend: append `nblocks` blocks of width dd to R (Algorithm 1, extension
+ * step: R <- [R, Rbar], S <- [S, A Rbar]) and compute only the new columns,
+ * all new blocks in one pass over A.  out_new->S receives the m x (nblocks*dd)
+ * new columns of S (and out_new->St those of S' when not NULL).  The input must
+ * be the same matrix the handle was applied to.  Asynchronous. */
+int sketch_extend(sk_handle *h, const sk_input *in, int32_t dd, int32_t nblocks,
+                  const sk_output *out_new, void *stream);
+
+/* sketch_rerun: redraw every block of the operator from `seed` (same widths) and
+ * recompute all d columns of S (and S') in one pass; allocates nothing once the
+ * handle exists.  out holds all d columns.  Asynchronous. */
+int sketch_rerun(sk_handle *h, const sk_input *in, uint64_t seed, const sk_output *out, void *stream);
+
+/* sketch_width: current total width d and number of blocks of the operator. */
+int sketch_width(const sk_handle *h, int32_t *d, int32_t *nblocks);
+
+/* sketch_release: free the operator metadata of a handle.  Synchronises the
+ * device before freeing.  SK_ESTATE for a released or foreign handle. */
+int sketch_release(sk_handle *h);
+
+/* sketch_get_rows: host evaluation of R(i0:i1, j0:j1) in FP64, column-major
+ * (out[(i - i0) + (j - j0) * ldo]), from the operator definition.
+ * Algorithm 1 needs R(I_tau, iota) for the diagonal-block corrections of the
+ * local sketches; section 7.2 gives the SRHT element formula used here.
+ * Requires 0 <= i0 <= i1 <= n, 0 <= j0 <= j1 <= d, ldo >= i1 - i0. */
+int sketch_get_rows(const sk_handle *h, int64_t i0, int64_t i1, int64_t j0, int64_t j1, double *out,
+                    int64_t ldo);
+
+/* sketch_get_sjlt: copy the device-generated hash of SJLT block `block` to host:
+ * codes[k * alpha + c] = (column inside the block << 1) | negative, for every row
+ * k < n and chunk c < alpha (section 6.1: R = (B+ - B-)/sqrt(alpha)).
+ * Synchronises.  SK_EINVAL if the handle is not SJLT or block is out of range. */
+int sketch_get_sjlt(const sk_handle *h, int32_t block, uint32_t *codes);
+
+/* sketch_get_srht: copy the device-generated SRHT data to host: D[k] in {+1,-1}
+ * for k < n (if D != NULL) and mu[j - j0] for global columns j0 <= j < j1 (if mu
+ * != NULL).  Section 7: D and P are stored as vectors, H is never formed.
+ * Synchronises. */
+int sketch_get_srht(const sk_handle *h, int8_t *D, uint32_t *mu, int32_t j0, int32_t j1);
+
+/* sketch_get_gaussian: copy the device-generated unscaled Gaussian draws of
+ * block `block` (n x w_b, column-major, bfloat16 bit patterns) to host.
+ * Synchronises. */
+int sketch_get_gaussian(const sk_handle *h, int32_t block, uint16_t *bits);
+
+/* sketch_profile_enable: when on != 0, every kernel launch made through this
+ * context is bracketed by HIP events recorded on the launch's own stream (the
+ * measurement behind achieved bandwidth; no effect on results). */
+int sketch_profile_enable(sk_ctx *ctx, int32_t on);
+
+/* sketch_profile_read: total elapsed milliseconds (*ms) and number of launches
+ * (*count) recorded for the kernel family `name` ("sjlt_gather",
+ * "sjlt_gather_t", "sjlt_reduce", "sjlt_meta", ...) since the last reset;
+ * reset != 0 clears every record.  Synchronises on the recorded events. */
+int sketch_profile_read(sk_ctx *ctx, const char *name, double *ms, int64_t *count, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSKETCH_SKETCH_H */

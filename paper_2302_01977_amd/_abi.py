@@ -1,0 +1,74 @@
+"""ctypes declarations of the C ABI in include/sketch.h (argument marshalling only).
+
+The shared library is built in-tree by ``paper_2302_01977_amd.build`` (or
+``__graft_entry__.build()``).  Loading fails loudly when it is missing: there is
+no fallback implementation of any sketch.
+"""
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhsketch.so")
+
+SK_OK, SK_EINVAL, SK_EUNSUPPORTED, SK_ENOMEM, SK_EHIP, SK_ESTATE = 0, -1, -2, -3, -4, -5
+SK_GAUSSIAN, SK_SJLT, SK_SRHT = 0, 1, 2
+SK_F64, SK_F32 = 0, 1
+SK_PREC_NATIVE, SK_PREC_BF16, SK_PREC_BF16X3 = 0, 1, 2
+SK_DENSE, SK_POINTS = 0, 1
+
+c_i32, c_i64, c_u64, c_f32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float, ctypes.c_void_p
+
+
+class SkInput(ctypes.Structure):
+    _fields_ = [("input", c_i32), ("dtype", c_i32), ("m", c_i64), ("n", c_i64), ("lda", c_i64),
+                ("A", c_vp), ("symmetric", c_i32), ("dim", c_i32), ("X", c_vp), ("N", c_i64),
+                ("h", c_f32), ("shift", c_f32)]
+
+
+class SkOpDesc(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("alpha", c_i32), ("prec", c_i32), ("flags", c_i32)]
+
+
+class SkOutput(ctypes.Structure):
+    _fields_ = [("S", c_vp), ("ldS", c_i64), ("St", c_vp), ("ldSt", c_i64)]
+
+
+P = ctypes.POINTER
+_SIGS = {
+    "sketch_init": (c_i32, [P(c_vp), c_i32]),
+    "sketch_finalize": (c_i32, [c_vp]),
+    "sketch_last_error": (ctypes.c_char_p, []),
+    "sketch_apply": (c_i32, [c_vp, P(SkInput), P(SkOpDesc), c_i32, c_u64, P(SkOutput), P(c_vp), c_vp]),
+    "sketch_extend": (c_i32, [c_vp, P(SkInput), c_i32, c_i32, P(SkOutput), c_vp]),
+    "sketch_rerun": (c_i32, [c_vp, P(SkInput), c_u64, P(SkOutput), c_vp]),
+    "sketch_width": (c_i32, [c_vp, P(c_i32), P(c_i32)]),
+    "sketch_release": (c_i32, [c_vp]),
+    "sketch_get_rows": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_i64, c_vp, c_i64]),
+    "sketch_get_sjlt": (c_i32, [c_vp, c_i32, c_vp]),
+    "sketch_get_srht": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32]),
+    "sketch_get_gaussian": (c_i32, [c_vp, c_i32, c_vp]),
+    "sketch_profile_enable": (c_i32, [c_vp, c_i32]),
+    "sketch_profile_read": (c_i32, [c_vp, ctypes.c_char_p, P(ctypes.c_double), P(c_i64), c_i32]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libhsketch.so once and declare every entry point."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libhsketch.so is not built (expected at %s); run "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_names():
+    return list(_SIGS)

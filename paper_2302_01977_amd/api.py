@@ -1,0 +1,223 @@
+"""Python layer over the C ABI: device memory and streams come from PyTorch, every
+step of every sketch runs in the library's HIP kernels.
+
+Matrices are column-major: a torch tensor of shape (m, n) with stride (1, ld),
+e.g. ``colmajor(m, n)`` or ``torch.from_numpy(A_fortran.T).T`` after upload.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi as abi
+
+KIND = {"gaussian": abi.SK_GAUSSIAN, "sjlt": abi.SK_SJLT, "srht": abi.SK_SRHT}
+PREC = {"native": abi.SK_PREC_NATIVE, "bf16": abi.SK_PREC_BF16, "bf16x3": abi.SK_PREC_BF16X3}
+
+
+class SketchError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("sketch error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(rc):
+    if rc != abi.SK_OK:
+        raise SketchError(rc, abi.load().sketch_last_error().decode())
+
+
+def colmajor(m, n, dtype=torch.float64, device="cuda"):
+    """Uninitialised column-major m x n tensor (shape (m, n), stride (1, m))."""
+    return torch.empty((n, m), dtype=dtype, device=device).T
+
+
+def to_device_colmajor(A, device="cuda"):
+    """Upload a numpy matrix as a column-major device tensor, values unchanged."""
+    A = np.asfortranarray(A)
+    return torch.from_numpy(A.T).to(device).T
+
+
+def _dtype_code(t):
+    if t == torch.float64:
+        return abi.SK_F64
+    if t == torch.float32:
+        return abi.SK_F32
+    raise ValueError("A must be float64 or float32")
+
+
+def _ld(t):
+    """Leading dimension of a column-major 2-D tensor (size-1 dims have free strides)."""
+    if t.dim() != 2 or (t.stride(0) != 1 and t.shape[0] > 1):
+        raise ValueError("expected a column-major 2-D tensor (stride(0) == 1)")
+    ld = t.stride(1) if t.shape[1] > 1 else t.shape[0]
+    if ld < t.shape[0]:
+        raise ValueError("leading dimension smaller than the row count")
+    return max(ld, 1)
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def dense_input(A, symmetric=False):
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    m, n = A.shape
+    return abi.SkInput(input=abi.SK_DENSE, dtype=_dtype_code(A.dtype), m=m, n=n, lda=_ld(A),
+                       A=A.data_ptr(), symmetric=int(bool(symmetric)))
+
+
+def points_input(X, h, shift=0.0):
+    if not X.is_cuda or X.dtype != torch.float32 or not X.is_contiguous() or X.dim() != 2:
+        raise ValueError("X must be a contiguous N x dim float32 device tensor")
+    return abi.SkInput(input=abi.SK_POINTS, dtype=abi.SK_F32, dim=X.shape[1], X=X.data_ptr(),
+                       N=X.shape[0], h=float(h), shift=float(shift))
+
+
+def _output(S, St):
+    o = abi.SkOutput(S=S.data_ptr(), ldS=_ld(S))
+    if St is not None:
+        o.St = St.data_ptr()
+        o.ldSt = _ld(St)
+    return o
+
+
+class Context:
+    """Per-device library context (sketch_init / sketch_finalize)."""
+
+    def __init__(self, device=0):
+        self._lib = abi.load()
+        self.ptr = ctypes.c_void_p()
+        _check(self._lib.sketch_init(ctypes.byref(self.ptr), device))
+        self.device = device
+
+    def profile(self, on=True):
+        _check(self._lib.sketch_profile_enable(self.ptr, int(bool(on))))
+
+    def profile_read(self, name, reset=False):
+        """(total ms, launches) recorded for a kernel family since the last reset."""
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        _check(self._lib.sketch_profile_read(self.ptr, name.encode(), ctypes.byref(ms), ctypes.byref(cnt),
+                                             int(bool(reset))))
+        return ms.value, cnt.value
+
+    def close(self):
+        if self.ptr:
+            _check(self._lib.sketch_finalize(self.ptr))
+            self.ptr = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Sketch:
+    """One operator R = [R_0 | R_1 | ...] applied to one input.
+
+    ``Sketch(ctx, A, "sjlt", d, seed, alpha=4, transpose=True)`` computes S = A R
+    (and S' = A^T R when ``transpose``) into ``self.S`` / ``self.St``.
+    """
+
+    def __init__(self, ctx, A, kind, d, seed, alpha=4, prec="native", transpose=False, symmetric=False,
+                 points=None, stream=None):
+        self._lib = abi.load()
+        self.ctx = ctx
+        self.kind = kind
+        self.symmetric = symmetric
+        if points is not None:
+            X, h, shift = points
+            self._in = points_input(X, h, shift)
+            rows, dtype, device = X.shape[0], torch.float32, X.device
+            self._keep = X
+        else:
+            self._in = dense_input(A, symmetric)
+            rows, dtype, device = A.shape[0], A.dtype, A.device
+            self._keep = A
+        self.rows = rows
+        self.dtype = dtype
+        self.device = device
+        self.transpose = transpose
+        op = abi.SkOpDesc(kind=KIND[kind], alpha=alpha, prec=PREC[prec], flags=0)
+        self.S = colmajor(rows, d, dtype, device)
+        self.St = colmajor(self._in.n, d, dtype, device) if transpose else None
+        self.h = ctypes.c_void_p()
+        _check(self._lib.sketch_apply(ctx.ptr, ctypes.byref(self._in), ctypes.byref(op), d, seed,
+                                      ctypes.byref(_output(self.S, self.St)), ctypes.byref(self.h),
+                                      _stream(stream)))
+
+    # -------------------------------------------------------------- growth
+    def extend(self, dd, nblocks=1, stream=None):
+        """Append nblocks blocks of width dd; computes only the new columns (one
+        pass) and returns them (S_new, St_new); self.S / self.St are grown."""
+        w = dd * nblocks
+        Sn = colmajor(self.rows, w, self.dtype, self.device)
+        Stn = colmajor(self._in.n, w, self.dtype, self.device) if self.transpose else None
+        _check(self._lib.sketch_extend(self.h, ctypes.byref(self._in), dd, nblocks,
+                                       ctypes.byref(_output(Sn, Stn)), _stream(stream)))
+        self.S = _hcat(self.S, Sn)
+        if self.transpose:
+            self.St = _hcat(self.St, Stn)
+        return Sn, Stn
+
+    def rerun(self, seed, stream=None):
+        """Redraw every block from ``seed`` and recompute all columns in place."""
+        _check(self._lib.sketch_rerun(self.h, ctypes.byref(self._in), seed,
+                                      ctypes.byref(_output(self.S, self.St)), _stream(stream)))
+
+    # -------------------------------------------------------------- queries
+    @property
+    def width(self):
+        d, nb = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.sketch_width(self.h, ctypes.byref(d), ctypes.byref(nb)))
+        return d.value, nb.value
+
+    def get_rows(self, i0, i1, j0, j1):
+        out = np.zeros((j1 - j0, i1 - i0), dtype=np.float64)  # column-major (i1-i0) x (j1-j0)
+        _check(self._lib.sketch_get_rows(self.h, i0, i1, j0, j1, out.ctypes.data, i1 - i0))
+        return out.T
+
+    def sjlt_codes(self, block, alpha):
+        n = self._in.N if self._in.input == abi.SK_POINTS else self._in.n
+        codes = np.zeros((n, alpha), dtype=np.uint32)
+        _check(self._lib.sketch_get_sjlt(self.h, block, codes.ctypes.data))
+        return codes
+
+    def srht_data(self, j0, j1):
+        n = self._in.n
+        D = np.zeros(n, dtype=np.int8)
+        mu = np.zeros(j1 - j0, dtype=np.uint32)
+        _check(self._lib.sketch_get_srht(self.h, D.ctypes.data, mu.ctypes.data, j0, j1))
+        return D, mu
+
+    def gaussian_bits(self, block, w):
+        n = self._in.N if self._in.input == abi.SK_POINTS else self._in.n
+        bits = np.zeros((w, n), dtype=np.uint16)
+        _check(self._lib.sketch_get_gaussian(self.h, block, bits.ctypes.data))
+        return bits.T
+
+    def release(self):
+        if self.h:
+            _check(self._lib.sketch_release(self.h))
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def _hcat(X, Y):
+    out = colmajor(X.shape[0], X.shape[1] + Y.shape[1], X.dtype, X.device)
+    out[:, :X.shape[1]] = X
+    out[:, X.shape[1]:] = Y
+    return out
+
+
+def bf16_bits_to_f64(bits):
+    """bfloat16 bit patterns -> FP64 values (exact)."""
+    u = np.asarray(bits, dtype=np.uint32) << np.uint32(16)
+    return u.view(np.float32).astype(np.float64)

@@ -1,0 +1,492 @@
+// C ABI: argument checking, handle bookkeeping, device metadata ownership and
+// dispatch to the kernel launchers.  Nothing here computes sketch values.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "internal.hpp"
+
+namespace sk {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error("%s failed: %s", what, hipGetErrorString(e));
+  return SK_EHIP;
+}
+
+static hipEvent_t pool_event(Ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ProfScope::ProfScope(Ctx* c_, const char* n_, hipStream_t s_) : c(c_), name(n_), st(s_) {
+  if (!c->prof) return;
+  a = pool_event(c);
+  if (a) (void)hipEventRecord(a, st);
+}
+
+ProfScope::~ProfScope() {
+  if (!a) return;
+  hipEvent_t b = pool_event(c);
+  if (!b) {
+    c->pool.push_back(a);
+    return;
+  }
+  (void)hipEventRecord(b, st);
+  c->recs.push_back(ProfRec{name, a, b});
+}
+
+int ensure_work(Ctx* c, size_t bytes) {
+  if (bytes <= c->work_bytes) return SK_OK;
+  if (c->work) {
+    SK_HIP(hipFree(c->work));  // implicit device synchronisation: no kernel still reads it
+    c->work = nullptr;
+    c->work_bytes = 0;
+  }
+  if (hipMalloc(&c->work, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    c->work = nullptr;
+    set_error("workspace allocation of %zu bytes failed", bytes);
+    return SK_ENOMEM;
+  }
+  c->work_bytes = bytes;
+  return SK_OK;
+}
+
+template <typename P>
+static int dev_alloc(P** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return SK_OK;
+  if (hipMalloc((void**)p, count * sizeof(P)) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    set_error("device allocation of %zu bytes failed", count * sizeof(P));
+    return SK_ENOMEM;
+  }
+  return SK_OK;
+}
+
+static void free_block(Block& b) {
+  if (b.codes) (void)hipFree(b.codes);
+  if (b.ptr) (void)hipFree(b.ptr);
+  if (b.ent) (void)hipFree(b.ent);
+  if (b.gbf) (void)hipFree(b.gbf);
+  if (b.gf64) (void)hipFree(b.gf64);
+  b = Block();
+}
+
+static bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+static int check_ctx(const sk_ctx* c) {
+  SK_REQUIRE(c && c->c.magic == CTX_MAGIC, SK_ESTATE, "not a live sketch context");
+  return SK_OK;
+}
+
+static int check_handle(const sk_handle* h) {
+  SK_REQUIRE(h && h->h.magic == HND_MAGIC, SK_ESTATE, "not a live sketch handle");
+  return SK_OK;
+}
+
+// rows of R implied by the input
+static int64_t op_rows(const sk_input* in) { return in->input == SK_POINTS ? in->N : in->n; }
+
+static int validate_input(const sk_input* in) {
+  SK_REQUIRE(in, SK_EINVAL, "input is NULL");
+  if (in->input == SK_DENSE) {
+    SK_REQUIRE(in->dtype == SK_F64 || in->dtype == SK_F32, SK_EINVAL, "dtype must be SK_F64 or SK_F32");
+    SK_REQUIRE(in->m >= 1 && in->n >= 1, SK_EINVAL, "A must have m >= 1 and n >= 1 (got %lld x %lld)",
+               (long long)in->m, (long long)in->n);
+    SK_REQUIRE(in->lda >= in->m, SK_EINVAL, "lda (%lld) < m (%lld)", (long long)in->lda, (long long)in->m);
+    SK_REQUIRE(in->A, SK_EINVAL, "A is NULL");
+    SK_REQUIRE(in->n <= 0x7fffffffLL && in->m <= 0x7fffffffLL, SK_EUNSUPPORTED, "dimensions above 2^31-1");
+  } else if (in->input == SK_POINTS) {
+    SK_REQUIRE(in->dtype == SK_F32, SK_EINVAL, "point input is FP32");
+    SK_REQUIRE(in->N >= 1 && in->N <= 0x7fffffffLL, SK_EINVAL, "N out of range");
+    SK_REQUIRE(in->dim >= 1 && in->dim <= 4, SK_EINVAL, "dim must be 1..4");
+    SK_REQUIRE(in->X, SK_EINVAL, "X is NULL");
+    SK_REQUIRE(in->h > 0.f, SK_EINVAL, "bandwidth h must be > 0");
+  } else {
+    SK_REQUIRE(false, SK_EINVAL, "unknown input kind %d", in->input);
+  }
+  return SK_OK;
+}
+
+static int validate_out(const sk_input* in, const sk_output* out, bool want_t) {
+  SK_REQUIRE(out && out->S, SK_EINVAL, "output S is NULL");
+  const int64_t rows = in->input == SK_POINTS ? in->N : in->m;
+  SK_REQUIRE(out->ldS >= rows, SK_EINVAL, "ldS (%lld) < rows (%lld)", (long long)out->ldS, (long long)rows);
+  if (want_t) {
+    SK_REQUIRE(in->input == SK_DENSE, SK_EINVAL, "S' is only defined for stored A");
+    SK_REQUIRE(in->m == in->n, SK_EINVAL, "S' = A^T R needs a square A (m == n)");
+    SK_REQUIRE(!in->symmetric, SK_EINVAL, "symmetric input: S' equals S, pass St = NULL");
+    SK_REQUIRE(out->ldSt >= in->n, SK_EINVAL, "ldSt < n");
+  }
+  return SK_OK;
+}
+
+static int validate_width(const Handle* h, int32_t w) {
+  SK_REQUIRE(w >= 1 && w <= 1024, SK_EINVAL, "block width must be in 1..1024 (got %d)", w);
+  if (h->kind == SK_SJLT) {
+    SK_REQUIRE(w % h->alpha == 0, SK_EINVAL, "alpha (%d) must divide the block width (%d)", h->alpha, w);
+  }
+  if (h->kind == SK_SJLT || h->kind == SK_SRHT) {
+    SK_REQUIRE(w % 16 == 0, SK_EINVAL, "SJLT/SRHT block widths must be multiples of 16 (got %d)", w);
+  }
+  return SK_OK;
+}
+
+static int add_block(Handle* h, int32_t w) {
+  Block b;
+  b.w = w;
+  b.index = (int32_t)h->blocks.size();
+  b.col0 = h->d;
+  int rc = SK_OK;
+  if (h->kind == SK_SJLT) {
+    const int64_t nT = (h->n + KC - 1) / KC;
+    if (!rc) rc = dev_alloc(&b.codes, (size_t)h->n * h->alpha);
+    if (!rc) rc = dev_alloc(&b.ptr, (size_t)nT * (w + 1));
+    // +8: the gather reads up to 7 entries past the end of a bucket (masked)
+    if (!rc) rc = dev_alloc(&b.ent, (size_t)h->n * h->alpha + 8);
+  } else if (h->kind == SK_GAUSSIAN) {
+    if (!rc) rc = dev_alloc(&b.gbf, (size_t)h->n * w);
+  } else if (h->kind == SK_SRHT) {
+    if (h->d + w > h->mu_cap) {
+      const int cap = std::max<int>(h->d + w, 2 * h->mu_cap);
+      uint32_t* nmu = nullptr;
+      rc = dev_alloc(&nmu, (size_t)cap);
+      if (!rc && h->srht_mu) {
+        SK_HIP(hipMemcpy(nmu, h->srht_mu, sizeof(uint32_t) * h->d, hipMemcpyDeviceToDevice));
+        (void)hipFree(h->srht_mu);
+      }
+      if (!rc) {
+        h->srht_mu = nmu;
+        h->mu_cap = cap;
+      }
+    }
+  }
+  if (rc) {
+    free_block(b);
+    return rc;
+  }
+  h->blocks.push_back(b);
+  h->d += w;
+  return SK_OK;
+}
+
+static int gen_block(Handle* h, int bi, hipStream_t st) {
+  Block& b = h->blocks[bi];
+  if (h->kind == SK_SJLT) return launch_sjlt_meta(h, b, st);
+  if (h->kind == SK_GAUSSIAN) return launch_gauss_meta(h, b, st);
+  return launch_srht_meta(h, b.col0, b.col0 + b.w, bi == 0, st);
+}
+
+static int compute_pass(Handle* h, const sk_input* in, int b0, int b1, const sk_output* out, hipStream_t st) {
+  if (in->input == SK_DENSE) {
+    if (h->kind == SK_SJLT) {
+      int rc = launch_sjlt_pass(h, in, b0, b1, false, out->S, out->ldS, st);
+      if (!rc && out->St) rc = launch_sjlt_pass(h, in, b0, b1, true, out->St, out->ldSt, st);
+      return rc;
+    }
+  }
+  set_error("operator kind %d with input kind %d is not available in this build", h->kind, in->input);
+  return SK_EUNSUPPORTED;
+}
+
+// split a run of blocks into passes of at most MAX_PASS_BLOCKS blocks
+static int compute_blocks(Handle* h, const sk_input* in, int b0, int b1, const sk_output* out, hipStream_t st) {
+  int64_t col = 0;
+  for (int p0 = b0; p0 < b1; p0 += MAX_PASS_BLOCKS) {
+    const int p1 = std::min(b1, p0 + MAX_PASS_BLOCKS);
+    const size_t esz = h->dtype == SK_F64 ? 8 : 4;
+    sk_output o = *out;
+    o.S = (char*)out->S + (size_t)col * out->ldS * esz;
+    if (out->St) o.St = (char*)out->St + (size_t)col * out->ldSt * esz;
+    const int rc = compute_pass(h, in, p0, p1, &o, st);
+    if (rc) return rc;
+    for (int b = p0; b < p1; ++b) col += h->blocks[b].w;
+  }
+  return SK_OK;
+}
+
+static int check_same_input(const Handle* h, const sk_input* in) {
+  SK_REQUIRE(in->input == h->input, SK_EINVAL, "input kind differs from the one the handle was applied to");
+  SK_REQUIRE(op_rows(in) == h->n, SK_EINVAL, "input size differs from the handle's operator (n = %lld)",
+             (long long)h->n);
+  SK_REQUIRE(in->input == SK_POINTS || in->dtype == h->dtype, SK_EINVAL, "dtype differs from the handle's");
+  return SK_OK;
+}
+
+}  // namespace sk
+
+using namespace sk;
+
+extern "C" {
+
+int sketch_init(sk_ctx** ctx, int32_t device) {
+  SK_REQUIRE(ctx, SK_EINVAL, "ctx is NULL");
+  *ctx = nullptr;
+  int count = 0;
+  SK_HIP(hipGetDeviceCount(&count));
+  SK_REQUIRE(device >= 0 && device < count, SK_EINVAL, "device %d out of range (%d devices)", device, count);
+  SK_HIP(hipSetDevice(device));
+  hipDeviceProp_t p;
+  SK_HIP(hipGetDeviceProperties(&p, device));
+  sk_ctx* c = new (std::nothrow) sk_ctx;
+  SK_REQUIRE(c, SK_ENOMEM, "host allocation failed");
+  c->c.device = device;
+  c->c.num_cu = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+  *ctx = c;
+  return SK_OK;
+}
+
+int sketch_finalize(sk_ctx* ctx) {
+  if (int rc = check_ctx(ctx)) return rc;
+  SK_REQUIRE(ctx->c.live_handles == 0, SK_ESTATE, "%d handles still live", ctx->c.live_handles);
+  SK_HIP(hipDeviceSynchronize());
+  if (ctx->c.work) (void)hipFree(ctx->c.work);
+  for (auto& r : ctx->c.recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : ctx->c.pool) (void)hipEventDestroy(e);
+  ctx->c.magic = 0;
+  delete ctx;
+  return SK_OK;
+}
+
+const char* sketch_last_error(void) { return g_err.c_str(); }
+
+int sketch_profile_enable(sk_ctx* ctx, int32_t on) {
+  if (int rc = check_ctx(ctx)) return rc;
+  ctx->c.prof = on != 0;
+  return SK_OK;
+}
+
+int sketch_profile_read(sk_ctx* ctx, const char* name, double* ms, int64_t* count, int32_t reset) {
+  if (int rc = check_ctx(ctx)) return rc;
+  SK_REQUIRE(name && ms && count, SK_EINVAL, "NULL argument");
+  Ctx* c = &ctx->c;
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (auto& r : c->recs) {
+    if (strcmp(r.name, name) != 0) continue;
+    SK_HIP(hipEventSynchronize(r.b));
+    float e = 0.f;
+    SK_HIP(hipEventElapsedTime(&e, r.a, r.b));
+    tot += e;
+    ++cnt;
+  }
+  *ms = tot;
+  *count = cnt;
+  if (reset) {
+    for (auto& r : c->recs) {
+      (void)hipEventSynchronize(r.b);
+      c->pool.push_back(r.a);
+      c->pool.push_back(r.b);
+    }
+    c->recs.clear();
+  }
+  return SK_OK;
+}
+
+int sketch_apply(sk_ctx* ctx, const sk_input* in, const sk_op_desc* op, int32_t d, uint64_t seed,
+                 const sk_output* out, sk_handle** hout, void* stream) {
+  if (int rc = check_ctx(ctx)) return rc;
+  SK_REQUIRE(hout, SK_EINVAL, "handle output pointer is NULL");
+  *hout = nullptr;
+  if (int rc = validate_input(in)) return rc;
+  SK_REQUIRE(op, SK_EINVAL, "operator description is NULL");
+  SK_REQUIRE(op->kind >= SK_GAUSSIAN && op->kind <= SK_SRHT, SK_EINVAL, "unknown operator kind %d", op->kind);
+  SK_REQUIRE(op->flags == 0, SK_EINVAL, "flags must be 0");
+  if (op->kind == SK_SJLT)
+    SK_REQUIRE(op->alpha >= 1 && op->alpha <= 32, SK_EINVAL, "alpha must be in 1..32 (got %d)", op->alpha);
+  if (op->kind == SK_SRHT)
+    SK_REQUIRE(is_pow2(op_rows(in)), SK_EUNSUPPORTED, "SRHT needs n a power of two (got %lld)",
+               (long long)op_rows(in));
+  SK_REQUIRE(op->prec >= SK_PREC_NATIVE && op->prec <= SK_PREC_BF16X3, SK_EINVAL, "unknown precision %d", op->prec);
+  if (op->kind == SK_GAUSSIAN && op->prec != SK_PREC_NATIVE)
+    SK_REQUIRE(in->dtype == SK_F32, SK_EINVAL, "bf16 Gaussian arithmetic needs FP32 A");
+  if (int rc = validate_out(in, out, out && out->St)) return rc;
+  SK_HIP(hipSetDevice(ctx->c.device));
+
+  sk_handle* H = new (std::nothrow) sk_handle;
+  SK_REQUIRE(H, SK_ENOMEM, "host allocation failed");
+  Handle* h = &H->h;
+  h->ctx = &ctx->c;
+  h->kind = op->kind;
+  h->alpha = op->kind == SK_SJLT ? op->alpha : 1;
+  h->prec = op->prec;
+  h->dtype = in->dtype;
+  h->input = in->input;
+  h->n = op_rows(in);
+  h->seed = seed;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = validate_width(h, d);
+  if (!rc && h->kind == SK_SRHT) rc = dev_alloc(&h->srht_D, (size_t)h->n);
+  if (!rc) rc = add_block(h, d);
+  if (!rc) rc = gen_block(h, 0, st);
+  if (!rc) rc = compute_blocks(h, in, 0, 1, out, st);
+  if (rc) {
+    const std::string msg = g_err;
+    (void)hipStreamSynchronize(st);
+    for (auto& b : h->blocks) free_block(b);
+    if (h->srht_D) (void)hipFree(h->srht_D);
+    if (h->srht_mu) (void)hipFree(h->srht_mu);
+    h->magic = 0;
+    delete H;
+    g_err = msg;
+    return rc;
+  }
+  ctx->c.live_handles++;
+  *hout = H;
+  return SK_OK;
+}
+
+int sketch_extend(sk_handle* H, const sk_input* in, int32_t dd, int32_t nblocks, const sk_output* out_new,
+                  void* stream) {
+  if (int rc = check_handle(H)) return rc;
+  Handle* h = &H->h;
+  if (int rc = validate_input(in)) return rc;
+  if (int rc = check_same_input(h, in)) return rc;
+  SK_REQUIRE(nblocks >= 1 && nblocks <= 64, SK_EINVAL, "nblocks must be in 1..64");
+  if (int rc = validate_width(h, dd)) return rc;
+  if (int rc = validate_out(in, out_new, out_new && out_new->St)) return rc;
+  SK_HIP(hipSetDevice(h->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int b0 = (int)h->blocks.size();
+  for (int i = 0; i < nblocks; ++i) {
+    if (int rc = add_block(h, dd)) return rc;
+    if (int rc = gen_block(h, b0 + i, st)) return rc;
+  }
+  return compute_blocks(h, in, b0, b0 + nblocks, out_new, st);
+}
+
+int sketch_rerun(sk_handle* H, const sk_input* in, uint64_t seed, const sk_output* out, void* stream) {
+  if (int rc = check_handle(H)) return rc;
+  Handle* h = &H->h;
+  if (int rc = validate_input(in)) return rc;
+  if (int rc = check_same_input(h, in)) return rc;
+  if (int rc = validate_out(in, out, out && out->St)) return rc;
+  SK_HIP(hipSetDevice(h->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  h->seed = seed;
+  for (int b = 0; b < (int)h->blocks.size(); ++b)
+    if (int rc = gen_block(h, b, st)) return rc;
+  return compute_blocks(h, in, 0, (int)h->blocks.size(), out, st);
+}
+
+int sketch_width(const sk_handle* H, int32_t* d, int32_t* nblocks) {
+  if (int rc = check_handle(H)) return rc;
+  if (d) *d = H->h.d;
+  if (nblocks) *nblocks = (int32_t)H->h.blocks.size();
+  return SK_OK;
+}
+
+int sketch_release(sk_handle* H) {
+  if (int rc = check_handle(H)) return rc;
+  Handle* h = &H->h;
+  SK_HIP(hipSetDevice(h->ctx->device));
+  SK_HIP(hipDeviceSynchronize());
+  for (auto& b : h->blocks) free_block(b);
+  if (h->srht_D) (void)hipFree(h->srht_D);
+  if (h->srht_mu) (void)hipFree(h->srht_mu);
+  h->ctx->live_handles--;
+  h->magic = 0;
+  delete H;
+  return SK_OK;
+}
+
+int sketch_get_rows(const sk_handle* H, int64_t i0, int64_t i1, int64_t j0, int64_t j1, double* out, int64_t ldo) {
+  if (int rc = check_handle(H)) return rc;
+  const Handle* h = &H->h;
+  SK_REQUIRE(0 <= i0 && i0 <= i1 && i1 <= h->n, SK_EINVAL, "row range out of bounds");
+  SK_REQUIRE(0 <= j0 && j0 <= j1 && j1 <= h->d, SK_EINVAL, "column range out of bounds");
+  SK_REQUIRE(out || i1 == i0 || j1 == j0, SK_EINVAL, "out is NULL");
+  SK_REQUIRE(ldo >= i1 - i0, SK_EINVAL, "ldo too small");
+  const Key key = key_of(h->seed);
+  for (int64_t j = j0; j < j1; ++j) {
+    int b = 0;
+    while (b + 1 < (int)h->blocks.size() && h->blocks[b + 1].col0 <= j) ++b;
+    const Block& B = h->blocks[b];
+    const int jj = (int)(j - B.col0);
+    double* o = out + (j - j0) * ldo;
+    if (h->kind == SK_SJLT) {
+      const uint32_t wc = (uint32_t)(B.w / h->alpha);
+      const uint32_t c = (uint32_t)jj / wc;
+      const double s = 1.0 / sqrt((double)h->alpha);
+      for (int64_t i = i0; i < i1; ++i) {
+        const uint32_t code = sjlt_code(key, (uint32_t)B.index, (uint32_t)i, c, wc);
+        o[i - i0] = ((int)(code >> 1) == jj) ? ((code & 1u) ? -s : s) : 0.0;
+      }
+    } else if (h->kind == SK_GAUSSIAN) {
+      const double sw = sqrt((double)B.w);
+      for (int64_t i = i0; i < i1; ++i) o[i - i0] = gauss_raw(key, (uint32_t)i, (uint32_t)j) / sw;
+    } else {
+      const uint32_t mu = srht_mu(key, (uint32_t)j, (uint32_t)h->n);
+      const double s = 1.0 / sqrt((double)B.w);
+      for (int64_t i = i0; i < i1; ++i) {
+        const int neg = srht_neg(key, (uint32_t)i) ^ (popc32((uint32_t)i & mu) & 1);
+        o[i - i0] = neg ? -s : s;
+      }
+    }
+  }
+  return SK_OK;
+}
+
+int sketch_get_sjlt(const sk_handle* H, int32_t block, uint32_t* codes) {
+  if (int rc = check_handle(H)) return rc;
+  const Handle* h = &H->h;
+  SK_REQUIRE(h->kind == SK_SJLT, SK_EINVAL, "handle is not an SJLT operator");
+  SK_REQUIRE(block >= 0 && block < (int)h->blocks.size(), SK_EINVAL, "block out of range");
+  SK_REQUIRE(codes, SK_EINVAL, "codes is NULL");
+  SK_HIP(hipSetDevice(h->ctx->device));
+  SK_HIP(hipDeviceSynchronize());
+  SK_HIP(hipMemcpy(codes, h->blocks[block].codes, sizeof(uint32_t) * h->n * h->alpha, hipMemcpyDeviceToHost));
+  return SK_OK;
+}
+
+int sketch_get_srht(const sk_handle* H, int8_t* D, uint32_t* mu, int32_t j0, int32_t j1) {
+  if (int rc = check_handle(H)) return rc;
+  const Handle* h = &H->h;
+  SK_REQUIRE(h->kind == SK_SRHT, SK_EINVAL, "handle is not an SRHT operator");
+  SK_REQUIRE(0 <= j0 && j0 <= j1 && j1 <= h->d, SK_EINVAL, "column range out of bounds");
+  SK_HIP(hipSetDevice(h->ctx->device));
+  SK_HIP(hipDeviceSynchronize());
+  if (D) SK_HIP(hipMemcpy(D, h->srht_D, (size_t)h->n, hipMemcpyDeviceToHost));
+  if (mu && j1 > j0) SK_HIP(hipMemcpy(mu, h->srht_mu + j0, sizeof(uint32_t) * (j1 - j0), hipMemcpyDeviceToHost));
+  return SK_OK;
+}
+
+int sketch_get_gaussian(const sk_handle* H, int32_t block, uint16_t* bits) {
+  if (int rc = check_handle(H)) return rc;
+  const Handle* h = &H->h;
+  SK_REQUIRE(h->kind == SK_GAUSSIAN, SK_EINVAL, "handle is not a Gaussian operator");
+  SK_REQUIRE(block >= 0 && block < (int)h->blocks.size(), SK_EINVAL, "block out of range");
+  SK_REQUIRE(bits, SK_EINVAL, "bits is NULL");
+  SK_HIP(hipSetDevice(h->ctx->device));
+  SK_HIP(hipDeviceSynchronize());
+  SK_HIP(hipMemcpy(bits, h->blocks[block].gbf, sizeof(uint16_t) * h->n * h->blocks[block].w,
+                   hipMemcpyDeviceToHost));
+  return SK_OK;
+}
+
+}  // extern "C"

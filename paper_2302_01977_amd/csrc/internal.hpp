@@ -1,0 +1,123 @@
+// Library-internal types shared by the ABI layer and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sketch.h"
+#include "spec.hpp"
+
+namespace sk {
+
+constexpr uint32_t CTX_MAGIC = 0x534b4358u;  // "SKCX"
+constexpr uint32_t HND_MAGIC = 0x534b4844u;  // "SKHD"
+constexpr int KC = 64;        // sources per chunk of the SJLT bucket tables
+constexpr int MAX_PASS_BLOCKS = 16;
+constexpr int MAX_PASS_GROUPS = 64;
+
+void set_error(const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+#define SK_HIP(call)                                  \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return ::sk::hip_fail(e_, #call); \
+  } while (0)
+
+#define SK_REQUIRE(cond, code, ...)  \
+  do {                               \
+    if (!(cond)) {                   \
+      ::sk::set_error(__VA_ARGS__);  \
+      return (code);                 \
+    }                                \
+  } while (0)
+
+struct Block {
+  int32_t w = 0;       // width w_b
+  int32_t index = 0;   // block number b (counter word of the SJLT hash)
+  int64_t col0 = 0;    // first global column c_b
+  // SJLT metadata
+  uint32_t* codes = nullptr;  // n * alpha: (col << 1) | neg
+  int32_t* ptr = nullptr;     // nT * (w + 1): bucket starts, chunk-major (ptr[t * (w + 1) + j])
+  int32_t* ent = nullptr;     // n * alpha (+8): (local source << 1) | neg, sorted by (chunk, col, source)
+  // Gaussian draws of the block: bf16 bits, n x w column-major (k contiguous)
+  uint16_t* gbf = nullptr;
+  // Gaussian draws as FP64, w x n (row j of R^T contiguous over k) for the FP64 kernel
+  double* gf64 = nullptr;
+};
+
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+struct Ctx {
+  uint32_t magic = CTX_MAGIC;
+  int device = 0;
+  int num_cu = 256;
+  int live_handles = 0;
+  void* work = nullptr;  // split-K partial sums, grow-only
+  size_t work_bytes = 0;
+  // launch timing (sketch_profile_*): events recorded around each kernel
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+};
+
+// Brackets one kernel launch with HIP events on its stream when profiling is on.
+struct ProfScope {
+  Ctx* c;
+  const char* name;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(Ctx* c_, const char* n_, hipStream_t s_);
+  ~ProfScope();
+};
+
+struct Handle {
+  uint32_t magic = HND_MAGIC;
+  Ctx* ctx = nullptr;
+  int32_t kind = 0, alpha = 1, prec = 0, dtype = 0, input = 0;
+  int64_t n = 0;  // rows of R
+  uint64_t seed = 0;
+  int32_t d = 0;
+  std::vector<Block> blocks;
+  // SRHT
+  int8_t* srht_D = nullptr;     // n signs (+1 / -1)
+  uint32_t* srht_mu = nullptr;  // capacity mu_cap
+  int32_t mu_cap = 0;
+};
+
+// Pass over a set of consecutive blocks: output column group g (of NJ columns)
+// reads block slot grp_blk[g] starting at column grp_col[g] of that block.
+struct SjltPass {
+  int32_t nT;       // number of source chunks of KC
+  int32_t wtot[MAX_PASS_BLOCKS];  // block widths (row length of ptr is w + 1)
+  int32_t ngroups;  // W / NJ
+  int32_t grp_blk[MAX_PASS_GROUPS];
+  int32_t grp_col[MAX_PASS_GROUPS];
+  const int32_t* ptr[MAX_PASS_BLOCKS];
+  const int32_t* ent[MAX_PASS_BLOCKS];
+};
+
+// ---- launchers (each returns SK_OK or an error code after checking the launch)
+int launch_sjlt_meta(Handle* h, Block& b, hipStream_t st);
+int launch_srht_meta(Handle* h, int64_t j0, int64_t j1, bool draw_D, hipStream_t st);
+int launch_gauss_meta(Handle* h, Block& b, hipStream_t st);
+
+// dense SJLT pass over blocks [b0, b1): S (trans = false) or S' (trans = true)
+int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, void* out, int64_t ldo,
+                     hipStream_t st);
+
+int ensure_work(Ctx* c, size_t bytes);
+
+}  // namespace sk
+
+struct sk_ctx {
+  sk::Ctx c;
+};
+struct sk_handle {
+  sk::Handle h;
+};

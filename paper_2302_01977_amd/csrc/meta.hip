@@ -1,0 +1,149 @@
+// Operator block generation on the device (random matrix construction; the paper
+// notes its cost is negligible next to the sketch, section 8 serial results).
+//
+// SJLT: the hash of every (row, chunk) and, per block, bucket tables that list
+// for each output column and each chunk of KC consecutive sources the sources
+// that feed it, in ascending order (a counting sort, deterministic).
+// SRHT: the Rademacher diagonal D and the sampled Hadamard columns mu.
+// Gaussian: the bf16-grid draws of the block, column-major.
+#include "internal.hpp"
+
+namespace sk {
+
+__global__ void __launch_bounds__(256) sjlt_hash_kernel(uint32_t* __restrict__ codes, int64_t n, int alpha,
+                                                        uint32_t wc, uint32_t block, Key key) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t sbits = philox(2u, block, (uint32_t)k, 0u, key.k0, key.k1).v[0];
+  for (int c4 = 0; c4 < alpha; c4 += 4) {
+    const U4 o = philox(1u, block, (uint32_t)k, (uint32_t)(c4 >> 2), key.k0, key.k1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = c4 + q;
+      if (c < alpha) {
+        const uint32_t off = mulhi(o.v[q], wc);
+        codes[k * alpha + c] = (((uint32_t)c * wc + off) << 1) | ((sbits >> c) & 1u);
+      }
+    }
+  }
+}
+
+// Bucket table, chunk-major: ptr[t * (w + 1) + j] = first entry of column j in
+// chunk t.  The count kernel stores counts there with slot w of every chunk set
+// to 0, so that an exclusive scan of the whole table gives the bucket starts and,
+// in slot w, the end of the chunk.
+__global__ void __launch_bounds__(256) sjlt_count_kernel(const uint32_t* __restrict__ codes,
+                                                         int32_t* __restrict__ ptr, int64_t n, int alpha,
+                                                         int w) {
+  __shared__ int cnt[1024];
+  const int t = blockIdx.x;
+  for (int j = threadIdx.x; j < w; j += blockDim.x) cnt[j] = 0;
+  __syncthreads();
+  const int64_t k0 = (int64_t)t * KC;
+  const int nk = (int)min((int64_t)KC, n - k0);
+  for (int e = threadIdx.x; e < nk * alpha; e += blockDim.x) atomicAdd(&cnt[codes[k0 * alpha + e] >> 1], 1);
+  __syncthreads();
+  for (int j = threadIdx.x; j <= w; j += blockDim.x) ptr[(int64_t)t * (w + 1) + j] = j < w ? cnt[j] : 0;
+}
+
+// In-place exclusive scan of M ints with one workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024) exclusive_scan_kernel(int32_t* __restrict__ a, int64_t M) {
+  __shared__ int32_t part[1024];
+  const int tid = threadIdx.x;
+  const int64_t seg = (M + 1023) / 1024;
+  const int64_t s0 = min(M, tid * seg), s1 = min(M, s0 + seg);
+  int32_t sum = 0;
+  for (int64_t i = s0; i < s1; ++i) sum += a[i];
+  part[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int32_t run = part[tid] - sum;
+  for (int64_t i = s0; i < s1; ++i) {
+    const int32_t c = a[i];
+    a[i] = run;
+    run += c;
+  }
+}
+
+__global__ void __launch_bounds__(KC) sjlt_scatter_kernel(const uint32_t* __restrict__ codes,
+                                                          const int32_t* __restrict__ ptr,
+                                                          int32_t* __restrict__ ent, int64_t n, int alpha,
+                                                          int w) {
+  __shared__ uint32_t sc[KC * 32];
+  const int t = blockIdx.x;
+  const int kk = threadIdx.x;
+  const int64_t k0 = (int64_t)t * KC;
+  const int nk = (int)min((int64_t)KC, n - k0);
+  for (int e = threadIdx.x; e < nk * alpha; e += blockDim.x) sc[e] = codes[k0 * alpha + e];
+  __syncthreads();
+  if (kk >= nk) return;
+  for (int c = 0; c < alpha; ++c) {
+    const uint32_t code = sc[kk * alpha + c];
+    const uint32_t col = code >> 1;
+    int rank = 0;
+    for (int q = 0; q < kk; ++q) rank += (sc[q * alpha + c] >> 1) == col;
+    ent[ptr[(int64_t)t * (w + 1) + col] + rank] = (kk << 1) | (int)(code & 1u);
+  }
+}
+
+int launch_sjlt_meta(Handle* h, Block& b, hipStream_t st) {
+  const int64_t n = h->n;
+  const int nT = (int)((n + KC - 1) / KC);
+  const uint32_t wc = (uint32_t)(b.w / h->alpha);
+  const Key key = key_of(h->seed);
+  ProfScope ps(h->ctx, "sjlt_meta", st);
+  sjlt_hash_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(b.codes, n, h->alpha, wc, (uint32_t)b.index, key);
+  SK_HIP(hipGetLastError());
+  sjlt_count_kernel<<<nT, 256, 0, st>>>(b.codes, b.ptr, n, h->alpha, b.w);
+  SK_HIP(hipGetLastError());
+  exclusive_scan_kernel<<<1, 1024, 0, st>>>(b.ptr, (int64_t)nT * (b.w + 1));
+  SK_HIP(hipGetLastError());
+  sjlt_scatter_kernel<<<nT, KC, 0, st>>>(b.codes, b.ptr, b.ent, n, h->alpha, b.w);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+__global__ void __launch_bounds__(256) srht_D_kernel(int8_t* __restrict__ D, int64_t n, Key key) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) D[k] = srht_neg(key, (uint32_t)k) ? (int8_t)-1 : (int8_t)1;
+}
+
+__global__ void __launch_bounds__(256) srht_mu_kernel(uint32_t* __restrict__ mu, int64_t j0, int64_t j1,
+                                                      uint32_t nu, Key key) {
+  const int64_t j = j0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < j1) mu[j] = srht_mu(key, (uint32_t)j, nu);
+}
+
+int launch_srht_meta(Handle* h, int64_t j0, int64_t j1, bool draw_D, hipStream_t st) {
+  const Key key = key_of(h->seed);
+  if (draw_D) {
+    srht_D_kernel<<<(unsigned)((h->n + 255) / 256), 256, 0, st>>>(h->srht_D, h->n, key);
+    SK_HIP(hipGetLastError());
+  }
+  if (j1 > j0) {
+    srht_mu_kernel<<<(unsigned)((j1 - j0 + 255) / 256), 256, 0, st>>>(h->srht_mu, j0, j1, (uint32_t)h->n, key);
+    SK_HIP(hipGetLastError());
+  }
+  return SK_OK;
+}
+
+__global__ void __launch_bounds__(256) gauss_kernel(uint16_t* __restrict__ g, int64_t n, int w, int64_t col0,
+                                                    Key key) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int jj = blockIdx.y;
+  if (k < n) g[k + (int64_t)jj * n] = bf16_bits_of_grid_value(gauss_raw(key, (uint32_t)k, (uint32_t)(col0 + jj)));
+}
+
+int launch_gauss_meta(Handle* h, Block& b, hipStream_t st) {
+  dim3 grid((unsigned)((h->n + 255) / 256), (unsigned)b.w);
+  gauss_kernel<<<grid, 256, 0, st>>>(b.gbf, h->n, b.w, b.col0, key_of(h->seed));
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+}  // namespace sk

@@ -1,0 +1,158 @@
+"""GPU parity of the SJLT path against the FP64 oracle (through the C ABI)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import operators as ops
+from oracle import sketch as osk
+
+pytestmark = pytest.mark.gpu
+
+TOL = {np.float64: 1e-12, np.float32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2302_01977_amd import api
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = api.Context(0)
+    yield c
+    import gc
+    gc.collect()
+    c.close()
+
+
+def _api():
+    from paper_2302_01977_amd import api
+    return api
+
+
+@pytest.mark.parametrize("n,w,alpha,block,seed", [(1000, 64, 4, 0, 5), (4096, 256, 4, 0, 6),
+                                                  (333, 32, 8, 0, 9), (64, 16, 1, 0, 1)])
+def test_hash_bit_exact(ctx, n, w, alpha, block, seed):
+    api = _api()
+    A = api.to_device_colmajor(np.ones((1, n)))
+    sk = api.Sketch(ctx, A, "sjlt", w, seed, alpha=alpha)
+    codes = sk.sjlt_codes(0, alpha)
+    cols, signs = ops.sjlt_hash(n, w, alpha, block, seed)
+    assert np.array_equal(codes >> 1, cols)
+    assert np.array_equal(codes & 1, (signs < 0).astype(np.uint32))
+    sk.release()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("m,n,w,alpha", [(1000, 1000, 64, 4), (1024, 1024, 256, 4), (777, 777, 64, 8),
+                                         (130, 70, 32, 4), (65, 4097, 48, 16)])
+def test_sketch_parity(ctx, dtype, m, n, w, alpha):
+    api = _api()
+    A = workloads.random_dense(m, n, 11, dtype)
+    Ad = api.to_device_colmajor(A)
+    square = m == n
+    sk = api.Sketch(ctx, Ad, "sjlt", w, 123, alpha=alpha, transpose=square)
+    torch.cuda.synchronize()
+    R = ops.sjlt_block(n, w, alpha, 0, 123)
+    A64 = A.astype(np.float64)
+    assert osk.rel_fro(sk.S.cpu().numpy(), osk.sketch(A64, R)) <= TOL[dtype]
+    if square:
+        assert osk.rel_fro(sk.St.cpu().numpy(), osk.sketch_t(A64, R)) <= TOL[dtype]
+    sk.release()
+
+
+def test_extension_multiblock_and_determinism(ctx):
+    api = _api()
+    n = 2048
+    A = workloads.random_dense(n, n, 2, np.float64)
+    Ad = api.to_device_colmajor(A)
+    sk = api.Sketch(ctx, Ad, "sjlt", 64, 77, alpha=4, transpose=True)
+    Sn, Stn = sk.extend(64, nblocks=3)          # three new blocks in one pass
+    sk.extend(128, nblocks=1)
+    torch.cuda.synchronize()
+    assert sk.width == (64 + 192 + 128, 5)
+    R = ops.operator("sjlt", n, [64, 64, 64, 64, 128], 77, alpha=4)
+    assert osk.rel_fro(sk.S.cpu().numpy(), A @ R) <= 1e-12
+    assert osk.rel_fro(sk.St.cpu().numpy(), A.T @ R) <= 1e-12
+    # same blocks drawn one at a time give bit-identical columns
+    sk2 = api.Sketch(ctx, Ad, "sjlt", 64, 77, alpha=4, transpose=True)
+    for _ in range(3):
+        sk2.extend(64)
+    sk2.extend(128)
+    torch.cuda.synchronize()
+    assert torch.equal(sk.S, sk2.S) and torch.equal(sk.St, sk2.St)
+    # rerun with the same seed reproduces everything bit for bit
+    S0 = sk.S.clone()
+    sk.rerun(77)
+    torch.cuda.synchronize()
+    assert torch.equal(S0, sk.S)
+    # rerun with a new seed matches the oracle's operator for that seed
+    sk.rerun(78)
+    torch.cuda.synchronize()
+    R78 = ops.operator("sjlt", n, [64, 64, 64, 64, 128], 78, alpha=4)
+    assert osk.rel_fro(sk.S.cpu().numpy(), A @ R78) <= 1e-12
+    sk.release()
+    sk2.release()
+
+
+def test_identity_gives_R_and_linearity(ctx):
+    api = _api()
+    n, w = 512, 64
+    I = api.to_device_colmajor(np.eye(n))
+    sk = api.Sketch(ctx, I, "sjlt", w, 5, alpha=4, transpose=True)
+    torch.cuda.synchronize()
+    R = ops.sjlt_block(n, w, 4, 0, 5)
+    assert np.array_equal(sk.S.cpu().numpy(), R)
+    assert np.array_equal(sk.St.cpu().numpy(), R)
+    sk.release()
+    A = workloads.random_dense(n, n, 1)
+    B = workloads.random_dense(n, n, 2)
+    outs = []
+    for M in (A, B, 2 * A - 3 * B):
+        s = api.Sketch(ctx, api.to_device_colmajor(M), "sjlt", w, 5, alpha=4)
+        torch.cuda.synchronize()
+        outs.append(s.S.cpu().numpy())
+        s.release()
+    assert osk.rel_fro(outs[2], 2 * outs[0] - 3 * outs[1]) < 1e-13
+
+
+def test_get_rows_matches_oracle(ctx):
+    api = _api()
+    n = 300
+    A = api.to_device_colmajor(np.ones((2, n)))
+    sk = api.Sketch(ctx, A, "sjlt", 32, 4, alpha=4)
+    sk.extend(48)
+    R = ops.operator("sjlt", n, [32, 48], 4, alpha=4)
+    assert np.array_equal(sk.get_rows(0, n, 0, 80), R)
+    assert np.array_equal(sk.get_rows(17, 250, 30, 70), R[17:250, 30:70])
+    sk.release()
+
+
+def test_argument_errors(ctx):
+    api = _api()
+    A = api.to_device_colmajor(np.ones((8, 8)))
+    with pytest.raises(api.SketchError) as e:
+        api.Sketch(ctx, A, "sjlt", 30, 1, alpha=4)      # alpha does not divide 30
+    assert e.value.code == -1
+    with pytest.raises(api.SketchError) as e:
+        api.Sketch(ctx, api.to_device_colmajor(np.ones((8, 12))), "srht", 16, 1)
+    assert e.value.code == -2                          # SRHT needs a power of two
+    A2 = api.to_device_colmajor(np.ones((8, 12)))
+    with pytest.raises(api.SketchError):
+        api.Sketch(ctx, A2, "sjlt", 16, 1, alpha=4, transpose=True)   # S' needs square A
+
+
+def test_cauchy_full_size_sampled_columns(ctx):
+    """The n = 16384 FP64 Cauchy workload at d = 256: S and S' on the GPU, 64
+    seeded columns of each checked against the oracle (sampled-column form)."""
+    api = _api()
+    c = workloads.cfg2()
+    A, n, d = c["A"], c["n"], c["d"]
+    Ad = api.to_device_colmajor(A)
+    sk = api.Sketch(ctx, Ad, "sjlt", d, c["seed"], alpha=c["alpha"], transpose=True)
+    torch.cuda.synchronize()
+    cols = workloads.sample_columns(d, 64, 99)
+    ref = osk.sketch_columns(A, "sjlt", n, [d], c["seed"], cols, alpha=4)
+    reft = osk.sketch_columns(A, "sjlt", n, [d], c["seed"], cols, alpha=4, transpose=True)
+    assert osk.rel_fro(sk.S[:, cols].cpu().numpy(), ref) <= 1e-12
+    assert osk.rel_fro(sk.St[:, cols].cpu().numpy(), reft) <= 1e-12
+    sk.release()
