@@ -23,24 +23,32 @@ def sketch_t(A, R):
     return np.asarray(A, dtype=np.float64).T @ np.asarray(R, dtype=np.float64)
 
 
-def sketch_columns(A, kind, n, widths, seed, cols, alpha=4, transpose=False):
-    """Selected columns of S (or S') without forming all of R.
-
-    ``cols`` are global column indices of R.  For each one the column of R is
-    formed from the element formulas and S(:, j) = sum_k A(:, k) R(k, j).
-    """
-    A = np.asarray(A)
+def operator_columns(kind, n, widths, seed, cols, alpha=4):
+    """The selected global columns of R = [R_0 | R_1 | ...] (FP64, n x len(cols)),
+    each formed from its block's element formulas."""
     offs = np.cumsum([0] + list(widths))
-    out = np.zeros((A.shape[1] if transpose else A.shape[0], len(cols)))
+    Rsel = np.zeros((n, len(cols)))
+    cache = {}
     for t, j in enumerate(cols):
         b = int(np.searchsorted(offs, j, side="right") - 1)
-        Rb = ops.operator_block(kind, n, widths[b], b, int(offs[b]), seed, alpha)
-        r = Rb[:, j - offs[b]]
-        nz = np.nonzero(r)[0]
-        if transpose:
-            out[:, t] = A[nz, :].astype(np.float64).T @ r[nz]
-        else:
-            out[:, t] = A[:, nz].astype(np.float64) @ r[nz]
+        if b not in cache:
+            cache[b] = ops.operator_block(kind, n, widths[b], b, int(offs[b]), seed, alpha)
+        Rsel[:, t] = cache[b][:, j - offs[b]]
+    return Rsel
+
+
+def sketch_columns(A, kind, n, widths, seed, cols, alpha=4, transpose=False, block=4096):
+    """Selected columns of S = A R (or S' = A^T R): S(:, j) = sum_k A(:, k) R(k, j),
+    evaluated for the requested global columns j only, in FP64, over row blocks
+    of the result so that an FP32 A is promoted one block at a time."""
+    A = np.asarray(A)
+    Rsel = operator_columns(kind, n, widths, seed, cols, alpha)
+    rows = A.shape[1] if transpose else A.shape[0]
+    out = np.zeros((rows, len(cols)))
+    for r0 in range(0, rows, block):
+        r1 = min(rows, r0 + block)
+        blk = A[:, r0:r1].T if transpose else A[r0:r1, :]
+        out[r0:r1] = blk.astype(np.float64) @ Rsel
     return out
 
 

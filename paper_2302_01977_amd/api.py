@@ -87,10 +87,12 @@ class Context:
     """Per-device library context (sketch_init / sketch_finalize)."""
 
     def __init__(self, device=0):
+        import weakref
         self._lib = abi.load()
         self.ptr = ctypes.c_void_p()
         _check(self._lib.sketch_init(ctypes.byref(self.ptr), device))
         self.device = device
+        self._live = weakref.WeakSet()   # sketches to release before finalize
 
     def profile(self, on=True):
         _check(self._lib.sketch_profile_enable(self.ptr, int(bool(on))))
@@ -104,6 +106,8 @@ class Context:
 
     def close(self):
         if self.ptr:
+            for sk in list(self._live):
+                sk.release()
             _check(self._lib.sketch_finalize(self.ptr))
             self.ptr = ctypes.c_void_p()
 
@@ -147,6 +151,7 @@ class Sketch:
         _check(self._lib.sketch_apply(ctx.ptr, ctypes.byref(self._in), ctypes.byref(op), d, seed,
                                       ctypes.byref(_output(self.S, self.St)), ctypes.byref(self.h),
                                       _stream(stream)))
+        ctx._live.add(self)
 
     # -------------------------------------------------------------- growth
     def extend(self, dd, nblocks=1, stream=None):

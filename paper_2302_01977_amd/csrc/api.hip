@@ -161,10 +161,10 @@ static int add_block(Handle* h, int32_t w) {
   b.col0 = h->d;
   int rc = SK_OK;
   if (h->kind == SK_SJLT) {
-    const int64_t nT = (h->n + KC - 1) / KC;
+    const int64_t nT = (h->n + h->kc - 1) / h->kc;
     if (!rc) rc = dev_alloc(&b.codes, (size_t)h->n * h->alpha);
     if (!rc) rc = dev_alloc(&b.ptr, (size_t)nT * (w + 1));
-    // +8: the gather reads up to 7 entries past the end of a bucket (masked)
+    // +8: the gather fetches bucket entries eight at a time (the excess is unused)
     if (!rc) rc = dev_alloc(&b.ent, (size_t)h->n * h->alpha + 8);
   } else if (h->kind == SK_GAUSSIAN) {
     if (!rc) rc = dev_alloc(&b.gbf, (size_t)h->n * w);
@@ -201,11 +201,10 @@ static int gen_block(Handle* h, int bi, hipStream_t st) {
 
 static int compute_pass(Handle* h, const sk_input* in, int b0, int b1, const sk_output* out, hipStream_t st) {
   if (in->input == SK_DENSE) {
-    if (h->kind == SK_SJLT) {
-      int rc = launch_sjlt_pass(h, in, b0, b1, false, out->S, out->ldS, st);
-      if (!rc && out->St) rc = launch_sjlt_pass(h, in, b0, b1, true, out->St, out->ldSt, st);
-      return rc;
-    }
+    auto pass = h->kind == SK_SJLT ? launch_sjlt_pass : h->kind == SK_SRHT ? launch_srht_pass : launch_gauss_pass;
+    int rc = pass(h, in, b0, b1, false, out->S, out->ldS, st);
+    if (!rc && out->St) rc = pass(h, in, b0, b1, true, out->St, out->ldSt, st);
+    return rc;
   }
   set_error("operator kind %d with input kind %d is not available in this build", h->kind, in->input);
   return SK_EUNSUPPORTED;
@@ -340,8 +339,13 @@ int sketch_apply(sk_ctx* ctx, const sk_input* in, const sk_op_desc* op, int32_t 
   h->n = op_rows(in);
   h->seed = seed;
   hipStream_t st = (hipStream_t)stream;
+  if (h->kind == SK_SJLT) h->kc = sjlt_chunk_for(d, h->alpha);
   int rc = validate_width(h, d);
   if (!rc && h->kind == SK_SRHT) rc = dev_alloc(&h->srht_D, (size_t)h->n);
+  if (!rc && h->kind == SK_SRHT) {
+    if (h->dtype == SK_F64) rc = dev_alloc((double**)&h->srht_Dv, (size_t)h->n);
+    else rc = dev_alloc((float**)&h->srht_Dv, (size_t)h->n);
+  }
   if (!rc) rc = add_block(h, d);
   if (!rc) rc = gen_block(h, 0, st);
   if (!rc) rc = compute_blocks(h, in, 0, 1, out, st);
@@ -350,6 +354,7 @@ int sketch_apply(sk_ctx* ctx, const sk_input* in, const sk_op_desc* op, int32_t 
     (void)hipStreamSynchronize(st);
     for (auto& b : h->blocks) free_block(b);
     if (h->srht_D) (void)hipFree(h->srht_D);
+    if (h->srht_Dv) (void)hipFree(h->srht_Dv);
     if (h->srht_mu) (void)hipFree(h->srht_mu);
     h->magic = 0;
     delete H;
@@ -408,6 +413,7 @@ int sketch_release(sk_handle* H) {
   SK_HIP(hipDeviceSynchronize());
   for (auto& b : h->blocks) free_block(b);
   if (h->srht_D) (void)hipFree(h->srht_D);
+  if (h->srht_Dv) (void)hipFree(h->srht_Dv);
   if (h->srht_mu) (void)hipFree(h->srht_mu);
   h->ctx->live_handles--;
   h->magic = 0;

@@ -13,7 +13,7 @@ namespace sk {
 
 constexpr uint32_t CTX_MAGIC = 0x534b4358u;  // "SKCX"
 constexpr uint32_t HND_MAGIC = 0x534b4844u;  // "SKHD"
-constexpr int KC = 64;        // sources per chunk of the SJLT bucket tables
+constexpr int KC_MAX = 256;   // largest chunk of sources of the SJLT bucket tables
 constexpr int MAX_PASS_BLOCKS = 16;
 constexpr int MAX_PASS_GROUPS = 64;
 
@@ -81,11 +81,13 @@ struct Handle {
   Ctx* ctx = nullptr;
   int32_t kind = 0, alpha = 1, prec = 0, dtype = 0, input = 0;
   int64_t n = 0;  // rows of R
+  int32_t kc = 64;  // SJLT: sources per chunk of the bucket tables
   uint64_t seed = 0;
   int32_t d = 0;
   std::vector<Block> blocks;
   // SRHT
   int8_t* srht_D = nullptr;     // n signs (+1 / -1)
+  void* srht_Dv = nullptr;      // the same signs as +-1.0 in the element type
   uint32_t* srht_mu = nullptr;  // capacity mu_cap
   int32_t mu_cap = 0;
 };
@@ -110,8 +112,13 @@ int launch_gauss_meta(Handle* h, Block& b, hipStream_t st);
 // dense SJLT pass over blocks [b0, b1): S (trans = false) or S' (trans = true)
 int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, void* out, int64_t ldo,
                      hipStream_t st);
+int launch_srht_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, void* out, int64_t ldo,
+                     hipStream_t st);
+int launch_gauss_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, void* out, int64_t ldo,
+                      hipStream_t st);
 
 int ensure_work(Ctx* c, size_t bytes);
+int sjlt_chunk_for(int w, int alpha);
 
 }  // namespace sk
 

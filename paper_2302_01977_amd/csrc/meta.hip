@@ -34,13 +34,13 @@ __global__ void __launch_bounds__(256) sjlt_hash_kernel(uint32_t* __restrict__ c
 // in slot w, the end of the chunk.
 __global__ void __launch_bounds__(256) sjlt_count_kernel(const uint32_t* __restrict__ codes,
                                                          int32_t* __restrict__ ptr, int64_t n, int alpha,
-                                                         int w) {
+                                                         int w, int kc) {
   __shared__ int cnt[1024];
   const int t = blockIdx.x;
   for (int j = threadIdx.x; j < w; j += blockDim.x) cnt[j] = 0;
   __syncthreads();
-  const int64_t k0 = (int64_t)t * KC;
-  const int nk = (int)min((int64_t)KC, n - k0);
+  const int64_t k0 = (int64_t)t * kc;
+  const int nk = (int)min((int64_t)kc, n - k0);
   for (int e = threadIdx.x; e < nk * alpha; e += blockDim.x) atomicAdd(&cnt[codes[k0 * alpha + e] >> 1], 1);
   __syncthreads();
   for (int j = threadIdx.x; j <= w; j += blockDim.x) ptr[(int64_t)t * (w + 1) + j] = j < w ? cnt[j] : 0;
@@ -70,15 +70,18 @@ __global__ void __launch_bounds__(1024) exclusive_scan_kernel(int32_t* __restric
   }
 }
 
-__global__ void __launch_bounds__(KC) sjlt_scatter_kernel(const uint32_t* __restrict__ codes,
-                                                          const int32_t* __restrict__ ptr,
-                                                          int32_t* __restrict__ ent, int64_t n, int alpha,
-                                                          int w) {
-  __shared__ uint32_t sc[KC * 32];
+// One workgroup per chunk, one thread per source; a source's rank inside its
+// bucket counts the earlier sources of the chunk in the same bucket, so every
+// bucket lists its sources in ascending order.
+__global__ void __launch_bounds__(KC_MAX) sjlt_scatter_kernel(const uint32_t* __restrict__ codes,
+                                                              const int32_t* __restrict__ ptr,
+                                                              int32_t* __restrict__ ent, int64_t n, int alpha,
+                                                              int w, int kc) {
+  __shared__ uint32_t sc[KC_MAX * 32];
   const int t = blockIdx.x;
   const int kk = threadIdx.x;
-  const int64_t k0 = (int64_t)t * KC;
-  const int nk = (int)min((int64_t)KC, n - k0);
+  const int64_t k0 = (int64_t)t * kc;
+  const int nk = (int)min((int64_t)kc, n - k0);
   for (int e = threadIdx.x; e < nk * alpha; e += blockDim.x) sc[e] = codes[k0 * alpha + e];
   __syncthreads();
   if (kk >= nk) return;
@@ -93,24 +96,29 @@ __global__ void __launch_bounds__(KC) sjlt_scatter_kernel(const uint32_t* __rest
 
 int launch_sjlt_meta(Handle* h, Block& b, hipStream_t st) {
   const int64_t n = h->n;
-  const int nT = (int)((n + KC - 1) / KC);
+  const int kc = h->kc;
+  const int nT = (int)((n + kc - 1) / kc);
   const uint32_t wc = (uint32_t)(b.w / h->alpha);
   const Key key = key_of(h->seed);
   ProfScope ps(h->ctx, "sjlt_meta", st);
   sjlt_hash_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(b.codes, n, h->alpha, wc, (uint32_t)b.index, key);
   SK_HIP(hipGetLastError());
-  sjlt_count_kernel<<<nT, 256, 0, st>>>(b.codes, b.ptr, n, h->alpha, b.w);
+  sjlt_count_kernel<<<nT, 256, 0, st>>>(b.codes, b.ptr, n, h->alpha, b.w, kc);
   SK_HIP(hipGetLastError());
   exclusive_scan_kernel<<<1, 1024, 0, st>>>(b.ptr, (int64_t)nT * (b.w + 1));
   SK_HIP(hipGetLastError());
-  sjlt_scatter_kernel<<<nT, KC, 0, st>>>(b.codes, b.ptr, b.ent, n, h->alpha, b.w);
+  sjlt_scatter_kernel<<<nT, kc, 0, st>>>(b.codes, b.ptr, b.ent, n, h->alpha, b.w, kc);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }
 
-__global__ void __launch_bounds__(256) srht_D_kernel(int8_t* __restrict__ D, int64_t n, Key key) {
+template <typename T>
+__global__ void __launch_bounds__(256) srht_D_kernel(int8_t* __restrict__ D, T* __restrict__ Dv, int64_t n, Key key) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) D[k] = srht_neg(key, (uint32_t)k) ? (int8_t)-1 : (int8_t)1;
+  if (k >= n) return;
+  const int neg = srht_neg(key, (uint32_t)k);
+  D[k] = neg ? (int8_t)-1 : (int8_t)1;
+  Dv[k] = neg ? T(-1) : T(1);
 }
 
 __global__ void __launch_bounds__(256) srht_mu_kernel(uint32_t* __restrict__ mu, int64_t j0, int64_t j1,
@@ -122,7 +130,9 @@ __global__ void __launch_bounds__(256) srht_mu_kernel(uint32_t* __restrict__ mu,
 int launch_srht_meta(Handle* h, int64_t j0, int64_t j1, bool draw_D, hipStream_t st) {
   const Key key = key_of(h->seed);
   if (draw_D) {
-    srht_D_kernel<<<(unsigned)((h->n + 255) / 256), 256, 0, st>>>(h->srht_D, h->n, key);
+    const unsigned nb = (unsigned)((h->n + 255) / 256);
+    if (h->dtype == SK_F64) srht_D_kernel<double><<<nb, 256, 0, st>>>(h->srht_D, (double*)h->srht_Dv, h->n, key);
+    else srht_D_kernel<float><<<nb, 256, 0, st>>>(h->srht_D, (float*)h->srht_Dv, h->n, key);
     SK_HIP(hipGetLastError());
   }
   if (j1 > j0) {

@@ -1,30 +1,86 @@
 // SJLT sketch of a stored, column-major A (section 6.3 computes A R by an outer
 // product over the rows of R and A^* R by inner products with the columns of R).
 //
-// GPU formulation: a hashed gather.  A workgroup owns 64 "lanes" (rows of A for
-// S = A R, columns of A for S' = A^T R) and walks the sources (columns of A for
-// S, rows for S') in chunks of KC = 64.  Each chunk is staged once, coalesced,
-// in LDS; every wave then owns NJ output columns and, for each of them, adds or
-// subtracts the staged sources listed in that column's bucket for the chunk
-// (wave-uniform indices, so every LDS read is a contiguous 64-lane access).
-// Accumulators stay in VGPRs; no multiplies, the 1/sqrt(alpha) scale is applied
-// once at the end, as in the paper.  When the lane tiles alone cannot fill the
-// chip the source range is split and the partial sums are reduced in a fixed
-// order (deterministic, no atomics).
+// GPU formulation: a hashed gather.  A workgroup owns TL = 64 * RPL "lanes"
+// (rows of A for S = A R, columns of A for S' = A^T R; RPL consecutive lanes per
+// thread) and walks the sources (columns of A for S, rows for S') in chunks of
+// KC.  Each chunk is staged once in LDS; it is loaded with coalesced 16-byte
+// accesses into registers one chunk ahead, so HBM traffic overlaps the gather.
+// Every wave owns NJ output columns; for each of them it adds or subtracts the
+// staged sources listed in that column's bucket for the chunk.  Bucket entries
+// are wave-uniform, so each LDS read is a contiguous access of RPL elements per
+// lane and the sign is folded into an FMA with a uniform +-1.  Accumulators stay
+// in VGPRs; the 1/sqrt(alpha) scale is applied once at the end, as in the paper.
+// KC is chosen per operator so that a bucket holds about four entries per chunk.
+// When the lane tiles cannot fill the chip the source range is split and the
+// partial sums are reduced in a fixed order (deterministic, no atomics).
+//
+// S' stages a transposed tile: each thread loads VECN x VECN blocks (VECN
+// sources of VECN columns, one 16-byte load per column), transposes them in
+// registers and writes 16-byte chunks whose position within the tile row is
+// XOR-swizzled by the source index; both the writes and the per-lane reads are
+// then free of bank conflicts.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace sk {
 
-template <typename T, bool TRANS, int NW, int NJ>
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// 16-byte global load at a 4-byte aligned address (lda may be odd)
+__device__ __forceinline__ u32x4 ld16(const void* p) {
+  u32x4 v;
+  __builtin_memcpy(&v, p, 16);
+  return v;
+}
+
+template <typename T, int N>
+struct VecT;
+template <>
+struct VecT<float, 1> {
+  typedef float type;
+};
+template <>
+struct VecT<float, 2> {
+  typedef f32x2 type;
+};
+template <>
+struct VecT<float, 4> {
+  typedef f32x4 type;
+};
+template <>
+struct VecT<double, 1> {
+  typedef double type;
+};
+template <>
+struct VecT<double, 2> {
+  typedef f64x2 type;
+};
+
+template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK>
 __global__ void __launch_bounds__(NW * 64)
     sjlt_gather_kernel(const T* __restrict__ A, int64_t lda, int64_t L, int64_t K, SjltPass pass,
                        T* __restrict__ out, int64_t ldo, T scale, int split, T* __restrict__ part) {
-  constexpr int STRIDE = TRANS ? 65 : 64;
-  constexpr int DUMMY = KC << 1;  // entry that reads the all-zero tile row KC
-  __shared__ T tile[(KC + 1) * STRIDE];
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t l0 = (int64_t)blockIdx.x * 64;
+  constexpr int SZ = sizeof(T);
+  constexpr int VECN = 16 / SZ;  // elements per 16-byte vector
+  constexpr int TL = 64 * RPL;   // lanes (rows of A, or columns of A for S') per workgroup
+  constexpr int NTHR = NW * 64;
+  constexpr int NV = KCK * TL / (NTHR * VECN);  // 16-byte vectors per thread per chunk
+  constexpr int NRB = KCK / VECN;               // S': row blocks per chunk
+  static_assert((KCK * TL) % (NTHR * VECN) == 0, "tile must split evenly");
+  static_assert(!TRANS || NV % VECN == 0, "S' staging moves whole VECN x VECN blocks");
+  static_assert(RPL <= VECN, "a lane reads at most one 16-byte chunk");
+  typedef typename VecT<T, RPL>::type VT;
+
+  __shared__ __attribute__((aligned(16))) T tile[KCK * TL];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t l0 = (int64_t)blockIdx.x * TL;
   const int s = blockIdx.y;
   const int nT = pass.nT;
   const int t0 = (int)(((int64_t)nT * s) / split);
@@ -36,66 +92,170 @@ __global__ void __launch_bounds__(NW * 64)
   const int64_t prow = pass.wtot[blk] + 1;
   const int32_t* __restrict__ ptr = pass.ptr[blk] + jb;
   const int32_t* __restrict__ ent = pass.ent[blk];
-  if (threadIdx.x < STRIDE) tile[KC * STRIDE + threadIdx.x] = T(0);
 
-  T acc[NJ];
-#pragma unroll
-  for (int jj = 0; jj < NJ; ++jj) acc[jj] = T(0);
-
-  for (int t = t0; t < t1; ++t) {
-    const int64_t k0 = (int64_t)t * KC;
+  // ---------------------------------------------------------------- staging
+  u32x4 buf[NV];
+  // Per-thread geometry of the staged tile.  NTHR * VECN is a multiple of TL
+  // (S) and NTHR a multiple of NRB (S'), so each thread keeps the same row (S)
+  // or row block (S') in every vector and only a uniform column step changes.
+  constexpr int CSTEP = NTHR * VECN / TL;   // S: columns advanced per vector
+  constexpr int CBSTEP = NTHR / NRB;        // S': column blocks advanced per block
+  static_assert((NTHR * VECN) % TL == 0 && NTHR % NRB == 0, "staging geometry");
+  const int my_row = (tid * VECN) % TL;           // S: row inside the tile
+  const int my_col = (tid * VECN) / TL;           // S: first column
+  const int my_rb = tid % NRB;                    // S': row block
+  const int my_cb = tid / NRB;                    // S': first column block
+  auto vec_rc = [&](int it, int64_t& gr, int64_t& gc, int64_t k0) {
     if (!TRANS) {
-      const int64_t row = l0 + lane;
-      for (int kk = threadIdx.x >> 6; kk < KC; kk += NW) {
-        const int64_t col = k0 + kk;
-        tile[kk * STRIDE + lane] = (row < L && col < K) ? A[row + col * lda] : T(0);
+      gr = l0 + my_row;
+      gc = k0 + my_col + (int64_t)it * CSTEP;
+    } else {
+      gr = k0 + (int64_t)my_rb * VECN;
+      gc = l0 + ((int64_t)my_cb + (int64_t)(it / VECN) * CBSTEP) * VECN + (it % VECN);
+    }
+  };
+  auto load_chunk = [&](int t) {
+    const int64_t k0 = (int64_t)t * KCK;
+    const bool full = l0 + TL <= L && k0 + KCK <= K;  // uniform
+    if (full) {
+      int64_t gr, gc;
+      vec_rc(0, gr, gc, k0);
+      const T* base = A + gr + gc * lda;
+#pragma unroll
+      for (int it = 0; it < NV; ++it) {
+        const int64_t off = TRANS ? ((int64_t)(it / VECN) * CBSTEP * VECN + (it % VECN)) * lda
+                                  : (int64_t)it * CSTEP * lda;
+        buf[it] = ld16(base + off);
       }
     } else {
-      const int64_t row = k0 + lane;
-      for (int l = threadIdx.x >> 6; l < 64; l += NW) {
-        const int64_t col = l0 + l;
-        tile[lane * STRIDE + l] = (row < K && col < L) ? A[row + col * lda] : T(0);
+#pragma unroll
+      for (int it = 0; it < NV; ++it) {
+        int64_t gr, gc;
+        vec_rc(it, gr, gc, k0);
+        const int64_t rlim = TRANS ? K : L;
+        const bool cok = TRANS ? gc < L : gc < K;
+        const T* p = A + gr + gc * lda;
+        T v[VECN];
+#pragma unroll
+        for (int q = 0; q < VECN; ++q) v[q] = (cok && gr + q < rlim) ? p[q] : T(0);
+        __builtin_memcpy(&buf[it], v, 16);
       }
     }
+  };
+  auto store_chunk = [&]() {
+    if (!TRANS) {
+#pragma unroll
+      for (int it = 0; it < NV; ++it) *(u32x4*)(&tile[(my_col + it * CSTEP) * TL + my_row]) = buf[it];
+    } else {
+#pragma unroll
+      for (int ib = 0; ib < NV / VECN; ++ib) {
+        const int cb = my_cb + ib * CBSTEP;
+        const int pos = (cb ^ (my_rb & 15)) * VECN;
+        T blkv[VECN][VECN];  // [column][source]
+#pragma unroll
+        for (int j = 0; j < VECN; ++j) __builtin_memcpy(blkv[j], &buf[ib * VECN + j], 16);
+#pragma unroll
+        for (int i = 0; i < VECN; ++i) {
+          T rowv[VECN];
+#pragma unroll
+          for (int j = 0; j < VECN; ++j) rowv[j] = blkv[j][i];
+          __builtin_memcpy(&tile[(my_rb * VECN + i) * TL + pos], rowv, 16);
+        }
+      }
+    }
+  };
+
+  T acc[NJ][RPL];
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj)
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) acc[jj][r] = T(0);
+
+  // per-lane part of the LDS read address (bytes)
+  const int lane_elem = lane * RPL;
+  const uint32_t lane_q16 = (uint32_t)(lane_elem / VECN) * 16u;  // S': 16-byte chunk before the swizzle
+  const uint32_t lane_in = (uint32_t)(lane_elem % VECN) * SZ;     // S': offset inside the chunk
+  const uint32_t lane_off = (uint32_t)lane_elem * SZ;             // S
+  const char* tbase = (const char*)tile;
+
+  auto LD = [&](int v) -> VT {
+    const uint32_t src = (uint32_t)v >> 1;
+    uint32_t a;
+    if (!TRANS) {
+      a = src * (uint32_t)(TL * SZ) + lane_off;
+    } else {
+      const uint32_t key16 = ((src / VECN) & 15u) * 16u;
+      a = src * (uint32_t)(TL * SZ) + ((lane_q16 ^ key16) + lane_in);
+    }
+    return *(const VT*)(tbase + a);
+  };
+
+  // +-1 from the entry's sign bit, built with integer operations on the uniform
+  // entry so that it stays a scalar operand of the FMA
+  auto sgn = [](int v) -> T {
+    if constexpr (sizeof(T) == 4) {
+      return __builtin_bit_cast(float, ((uint32_t)v << 31) | 0x3f800000u);
+    } else {
+      return __builtin_bit_cast(double, ((uint64_t)(uint32_t)v << 63) | 0x3ff0000000000000ull);
+    }
+  };
+
+  if (t0 < t1) load_chunk(t0);
+  for (int t = t0; t < t1; ++t) {
+    __syncthreads();  // the previous chunk is fully consumed
+    store_chunk();
     __syncthreads();
+    if (t + 1 < t1) load_chunk(t + 1);  // in flight during the gather below
     if (active) {
       const int32_t* __restrict__ P = ptr + (int64_t)t * prow;
+      int pv[NJ + 1];  // bucket bounds of the wave's columns, loaded once per chunk
+#pragma unroll
+      for (int jj = 0; jj <= NJ; ++jj) pv[jj] = P[jj];
 #pragma unroll
       for (int jj = 0; jj < NJ; ++jj) {
-        const int p1 = P[jj + 1];
-        T a0 = T(0), a1 = T(0);
-        for (int e = P[jj]; e < p1; e += 4) {
-          // four entries per step, reads in flight together; past the end of
-          // the bucket the dummy entry adds the zero row
-          int v[4];
+        // accumulate straight into acc: separate partial sums per column get
+        // sunk to the end of the chunk by the compiler and inflate VGPR use
+        const int p1 = pv[jj + 1];
+        // up to eight entries per scalar load; all their LDS reads are issued
+        // before the first wait (entries past the bucket end are never used;
+        // the entry array carries 8 slots of padding)
+        for (int e = pv[jj]; e < p1; e += 8) {
+          const int rem = p1 - e;
+          int v[8];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) v[u] = (e + u < p1) ? ent[e + u] : DUMMY;
-          T x[4];
+          for (int u = 0; u < 8; ++u) v[u] = ent[e + u];
+          VT x[8];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) x[u] = tile[(v[u] >> 1) * STRIDE + lane];
+          for (int u = 0; u < 8; ++u)
+            if (u < rem) x[u] = LD(v[u]);
 #pragma unroll
-          for (int u = 0; u < 4; u += 2) {
-            a0 = fma(x[u], (v[u] & 1) ? T(-1) : T(1), a0);
-            a1 = fma(x[u + 1], (v[u + 1] & 1) ? T(-1) : T(1), a1);
-          }
+          for (int u = 0; u < 8; ++u)
+            if (u < rem) {
+              const T sg = sgn(v[u]);
+#pragma unroll
+              for (int r = 0; r < RPL; ++r) acc[jj][r] = fma(((const T*)&x[u])[r], sg, acc[jj][r]);
+            }
         }
-        acc[jj] += a0 + a1;
       }
     }
-    __syncthreads();
   }
 
   if (!active) return;
-  const int64_t row = l0 + lane;
-  if (row >= L) return;
+  const int64_t row0 = l0 + lane_elem;
   const int64_t jc = (int64_t)g * NJ;
-  if (split == 1) {
+  T* dst = out;
+  int64_t ldd = ldo;
+  T sc = scale;
+  if (split > 1) {
+    dst = part + (int64_t)s * L * ((int64_t)pass.ngroups * NJ);
+    ldd = L;
+    sc = T(1);
+  }
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) out[row + (jc + jj) * ldo] = acc[jj] * scale;
-  } else {
-    T* p = part + (int64_t)s * L * ((int64_t)pass.ngroups * NJ);
+  for (int jj = 0; jj < NJ; ++jj) {
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) p[row + (jc + jj) * L] = acc[jj];
+    for (int r = 0; r < RPL; ++r)
+      if (row0 + r < L) dst[row0 + r + (jc + jj) * ldd] = acc[jj][r] * sc;
   }
 }
 
@@ -110,29 +270,88 @@ __global__ void __launch_bounds__(256) split_reduce_kernel(const T* __restrict__
   out[row + j * ldo] = a * scale;
 }
 
-static thread_local Ctx* prof_ctx = nullptr;
+// ------------------------------------------------------------------ dispatch
+struct GatherCfg {
+  int nw, nj, rpl, kc;
+};
 
-template <typename T, bool TRANS, int NW, int NJ>
-static int run_gather(const T* A, int64_t lda, int64_t L, int64_t K, const SjltPass& pass, T* out, int64_t ldo,
-                      T scale, int split, T* part, int gz, hipStream_t st) {
-  dim3 grid((unsigned)((L + 63) / 64), (unsigned)split, (unsigned)gz);
-  ProfScope ps(prof_ctx, TRANS ? "sjlt_gather_t" : "sjlt_gather", st);
-  sjlt_gather_kernel<T, TRANS, NW, NJ><<<grid, NW * 64, 0, st>>>(A, lda, L, K, pass, out, ldo, scale, split, part);
+template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK>
+static int run_gather(Ctx* c, const T* A, int64_t lda, int64_t L, int64_t K, const SjltPass& pass, T* out,
+                      int64_t ldo, T scale, int split, T* part, int gz, hipStream_t st) {
+  dim3 grid((unsigned)((L + 64 * RPL - 1) / (64 * RPL)), (unsigned)split, (unsigned)gz);
+  ProfScope ps(c, TRANS ? "sjlt_gather_t" : "sjlt_gather", st);
+  sjlt_gather_kernel<T, TRANS, NW, NJ, RPL, KCK>
+      <<<grid, NW * 64, 0, st>>>(A, lda, L, K, pass, out, ldo, scale, split, part);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }
 
+template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK>
+struct GatherValid {
+  static constexpr int VECN = 16 / (int)sizeof(T);
+  static constexpr int NV = KCK * 64 * RPL / (NW * 64 * VECN);
+  static constexpr bool value = (KCK * 64 * RPL) % (NW * 64 * VECN) == 0 && NV >= 1 && (!TRANS || NV % VECN == 0) &&
+                                RPL <= VECN;
+};
+
+// returns 1 when the configuration does not match (caller tries the next one)
+template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK>
+static int try_cfg(const GatherCfg& cfg, Ctx* c, const T* A, int64_t lda, int64_t L, int64_t K, const SjltPass& pass,
+                   T* out, int64_t ldo, T scale, int split, T* part, int gz, hipStream_t st) {
+  if (cfg.nw != NW || cfg.nj != NJ || cfg.rpl != RPL || cfg.kc != KCK) return 1;
+  if constexpr (GatherValid<T, TRANS, NW, NJ, RPL, KCK>::value) {
+    return run_gather<T, TRANS, NW, NJ, RPL, KCK>(c, A, lda, L, K, pass, out, ldo, scale, split, part, gz, st);
+  } else {
+    return 1;
+  }
+}
+
+#define SK_TRY(NW_, NJ_, RPL_, KC_)                                                                              \
+  if ((rc = try_cfg<T, TRANS, NW_, NJ_, RPL_, KC_>(cfg, c, A, lda, L, K, pass, out, ldo, scale, split, part, gz, \
+                                                   st)) != 1)                                                   \
+    return rc;
+#define SK_TRY_NW(NJ_, RPL_, KC_) SK_TRY(4, NJ_, RPL_, KC_) SK_TRY(8, NJ_, RPL_, KC_)
+
 template <typename T, bool TRANS>
-static int dispatch(int nw, int nj, const T* A, int64_t lda, int64_t L, int64_t K, const SjltPass& pass, T* out,
-                    int64_t ldo, T scale, int split, T* part, int gz, hipStream_t st) {
-  if (nw == 4 && nj == 16) return run_gather<T, TRANS, 4, 16>(A, lda, L, K, pass, out, ldo, scale, split, part, gz, st);
-  if (nw == 4 && nj == 32) return run_gather<T, TRANS, 4, 32>(A, lda, L, K, pass, out, ldo, scale, split, part, gz, st);
-  if (nw == 4 && nj == 64) return run_gather<T, TRANS, 4, 64>(A, lda, L, K, pass, out, ldo, scale, split, part, gz, st);
-  if (nw == 8 && nj == 16) return run_gather<T, TRANS, 8, 16>(A, lda, L, K, pass, out, ldo, scale, split, part, gz, st);
-  if (nw == 8 && nj == 32) return run_gather<T, TRANS, 8, 32>(A, lda, L, K, pass, out, ldo, scale, split, part, gz, st);
-  if (nw == 8 && nj == 64) return run_gather<T, TRANS, 8, 64>(A, lda, L, K, pass, out, ldo, scale, split, part, gz, st);
-  set_error("internal: no SJLT kernel for NW=%d NJ=%d", nw, nj);
+static int dispatch(Ctx* c, const GatherCfg& cfg, const T* A, int64_t lda, int64_t L, int64_t K,
+                    const SjltPass& pass, T* out, int64_t ldo, T scale, int split, T* part, int gz,
+                    hipStream_t st) {
+  int rc;
+  if constexpr (sizeof(T) == 4) {
+    SK_TRY_NW(16, 4, 64)
+    SK_TRY_NW(16, 2, 128)
+    SK_TRY_NW(32, 2, 128)
+    SK_TRY_NW(16, 1, 64)
+    SK_TRY_NW(32, 1, 64)
+    SK_TRY_NW(64, 1, 64)
+    SK_TRY_NW(16, 1, 128)
+    SK_TRY_NW(32, 1, 128)
+    SK_TRY_NW(64, 1, 128)
+    SK_TRY_NW(16, 1, 256)
+    SK_TRY_NW(32, 1, 256)
+    SK_TRY_NW(64, 1, 256)
+  } else {
+    SK_TRY_NW(16, 2, 64)
+    SK_TRY_NW(16, 1, 64)
+    SK_TRY_NW(32, 1, 64)
+    SK_TRY_NW(16, 1, 128)
+    SK_TRY_NW(32, 1, 128)
+    SK_TRY_NW(16, 1, 256)
+    SK_TRY_NW(32, 1, 256)
+  }
+  set_error("internal: no SJLT kernel for NW=%d NJ=%d RPL=%d KC=%d", cfg.nw, cfg.nj, cfg.rpl, cfg.kc);
   return SK_EINVAL;
+}
+
+// the launch table skips 8-wave variants whose tile does not split evenly
+template <typename T, bool TRANS>
+static bool cfg_valid(int nw, int rpl, int kc) {
+  const int vecn = 16 / (int)sizeof(T);
+  const long tile = (long)kc * 64 * rpl;
+  const long per = (long)nw * 64 * vecn;
+  if (tile % per) return false;
+  const long nv = tile / per;
+  return nv >= 1 && (!TRANS || nv % vecn == 0) && rpl <= vecn;
 }
 
 static int gcd_int(int a, int b) {
@@ -144,6 +363,38 @@ static int gcd_int(int a, int b) {
   return a;
 }
 
+int sjlt_chunk_for(int w, int alpha) {
+  // about four entries per bucket and chunk: KC * alpha / w >= 4
+  int kc = 64;
+  while (kc < 256 && kc * alpha < 4 * w) kc *= 2;
+  return kc;
+}
+
+// rows per lane, columns per wave and waves per workgroup for a pass of width W
+// whose block widths share the divisor g
+static GatherCfg choose_cfg(int dtype, int kc, int W, int g) {
+  GatherCfg c;
+  c.kc = kc;
+  if (dtype == SK_F32) c.rpl = kc == 64 ? 4 : kc == 128 ? 2 : 1;
+  else c.rpl = kc == 64 ? 2 : 1;
+  // accumulators per lane stay at or below 64 VGPRs
+  int njmax = (dtype == SK_F32 ? 64 : 32) / c.rpl;
+  // a pass wider than 8 waves x njmax columns would re-read A: fewer rows per lane
+  if (W > 8 * njmax && c.rpl > 1) {
+    c.rpl = 1;
+    njmax = dtype == SK_F32 ? 64 : 32;
+  }
+  int nj = 16;
+  for (int cand = njmax; cand >= 16; cand /= 2)
+    if (g % cand == 0 && (cand * 4 <= W || cand == 16)) {
+      nj = cand;
+      break;
+    }
+  c.nj = nj;
+  c.nw = W / nj <= 4 ? 4 : 8;
+  return c;
+}
+
 int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, void* out, int64_t ldo,
                      hipStream_t st) {
   const int nblk = b1 - b0;
@@ -153,25 +404,22 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
     W += h->blocks[b].w;
     g = gcd_int(g, h->blocks[b].w);
   }
-  // columns per wave: the largest of 64/32/16 dividing every width, at most W/4
-  int nj = 16;
-  const int nj_max = h->dtype == SK_F64 ? 32 : 64;  // FP64 x 64 columns spills
-  for (int c : {64, 32}) {
-    if (c > nj_max) continue;
-    if (g % c == 0 && c <= (W >= 64 ? W / 4 : 16)) {
-      nj = c;
-      break;
-    }
+  SK_REQUIRE(g % 16 == 0, SK_EINVAL, "SJLT block widths must be multiples of 16");
+  GatherCfg cfg = choose_cfg(h->dtype, h->kc, W, g);
+  if (cfg.nw == 8) {
+    const bool ok = h->dtype == SK_F64 ? (trans ? cfg_valid<double, true>(8, cfg.rpl, cfg.kc)
+                                               : cfg_valid<double, false>(8, cfg.rpl, cfg.kc))
+                                       : (trans ? cfg_valid<float, true>(8, cfg.rpl, cfg.kc)
+                                                : cfg_valid<float, false>(8, cfg.rpl, cfg.kc));
+    if (!ok) cfg.nw = 4;
   }
-  SK_REQUIRE(g % nj == 0, SK_EINVAL, "SJLT block widths must be multiples of 16");
-  const int ngroups = W / nj;
+  const int ngroups = W / cfg.nj;
   SK_REQUIRE(ngroups <= MAX_PASS_GROUPS, SK_EINVAL, "pass too wide (%d columns)", W);
-  const int nw = ngroups <= 4 ? 4 : 8;
-  const int gz = (ngroups + nw - 1) / nw;
+  const int gz = (ngroups + cfg.nw - 1) / cfg.nw;
 
   SjltPass pass;
   memset(&pass, 0, sizeof(pass));
-  pass.nT = (int)((h->n + KC - 1) / KC);
+  pass.nT = (int)((h->n + h->kc - 1) / h->kc);
   pass.ngroups = ngroups;
   int gi = 0;
   for (int b = b0; b < b1; ++b) {
@@ -179,7 +427,7 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
     pass.ptr[b - b0] = B.ptr;
     pass.ent[b - b0] = B.ent;
     pass.wtot[b - b0] = B.w;
-    for (int c = 0; c < B.w; c += nj) {
+    for (int c = 0; c < B.w; c += cfg.nj) {
       pass.grp_blk[gi] = b - b0;
       pass.grp_col[gi] = c;
       ++gi;
@@ -188,11 +436,14 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
 
   const int64_t L = trans ? in->n : in->m;  // lanes
   const int64_t K = trans ? in->m : in->n;  // sources (= rows of R)
-  const int64_t tiles = ((L + 63) / 64) * gz;
-  int split = 1;
-  const int64_t target = 2 * (int64_t)h->ctx->num_cu;
-  if (tiles < target) split = (int)std::min<int64_t>((target + tiles - 1) / tiles, std::max(1, pass.nT / 4));
+  const int TL = 64 * cfg.rpl;
+  const int64_t tiles = ((L + TL - 1) / TL) * gz;
   const size_t esz = h->dtype == SK_F64 ? 8 : 4;
+  const size_t tile_bytes = (size_t)cfg.kc * TL * esz;
+  const int64_t per_cu = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)tile_bytes);
+  const int64_t target = per_cu * (int64_t)h->ctx->num_cu;
+  int split = 1;
+  if (tiles < target) split = (int)std::min<int64_t>((target + tiles - 1) / tiles, std::max(1, pass.nT / 4));
   void* part = nullptr;
   if (split > 1) {
     const int rc = ensure_work(h->ctx, (size_t)split * (size_t)L * (size_t)W * esz);
@@ -200,16 +451,20 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
     part = h->ctx->work;
   }
   const double scale = 1.0 / sqrt((double)h->alpha);
-  prof_ctx = h->ctx;
+  Ctx* c = h->ctx;
   int rc;
   if (h->dtype == SK_F64) {
     const double* A = (const double*)in->A;
-    rc = trans ? dispatch<double, true>(nw, nj, A, in->lda, L, K, pass, (double*)out, ldo, scale, split, (double*)part, gz, st)
-               : dispatch<double, false>(nw, nj, A, in->lda, L, K, pass, (double*)out, ldo, scale, split, (double*)part, gz, st);
+    rc = trans ? dispatch<double, true>(c, cfg, A, in->lda, L, K, pass, (double*)out, ldo, scale, split,
+                                        (double*)part, gz, st)
+               : dispatch<double, false>(c, cfg, A, in->lda, L, K, pass, (double*)out, ldo, scale, split,
+                                         (double*)part, gz, st);
   } else {
     const float* A = (const float*)in->A;
-    rc = trans ? dispatch<float, true>(nw, nj, A, in->lda, L, K, pass, (float*)out, ldo, (float)scale, split, (float*)part, gz, st)
-               : dispatch<float, false>(nw, nj, A, in->lda, L, K, pass, (float*)out, ldo, (float)scale, split, (float*)part, gz, st);
+    rc = trans ? dispatch<float, true>(c, cfg, A, in->lda, L, K, pass, (float*)out, ldo, (float)scale, split,
+                                       (float*)part, gz, st)
+               : dispatch<float, false>(c, cfg, A, in->lda, L, K, pass, (float*)out, ldo, (float)scale, split,
+                                        (float*)part, gz, st);
   }
   if (rc) return rc;
   if (split > 1) {
@@ -219,7 +474,8 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
     if (h->dtype == SK_F64)
       split_reduce_kernel<double><<<nb, 256, 0, st>>>((const double*)part, split, L, W, (double*)out, ldo, scale);
     else
-      split_reduce_kernel<float><<<nb, 256, 0, st>>>((const float*)part, split, L, W, (float*)out, ldo, (float)scale);
+      split_reduce_kernel<float><<<nb, 256, 0, st>>>((const float*)part, split, L, W, (float*)out, ldo,
+                                                     (float)scale);
     SK_HIP(hipGetLastError());
   }
   return SK_OK;
