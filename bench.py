@@ -20,6 +20,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+KERNELS = {"sjlt": ("sjlt_gather", "sjlt_gather_t", "sjlt_reduce", "sjlt_meta"),
+           "srht": ("srht", "srht_t"),
+           "gaussian": ("gauss_f64", "gauss_f64_t")}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 BF16_PEAK_TFLOPS = 2500.0
@@ -109,7 +112,7 @@ def main():
             sk.rerun(seed + 1000 + i)
         torch.cuda.synchronize()
         kern = {}
-        for name in ("sjlt_gather", "sjlt_gather_t", "sjlt_reduce", "sjlt_meta"):
+        for name in KERNELS[kind]:
             tot, cnt = ctx.profile_read(name)
             if cnt:
                 kern[name] = {"avg_ms": tot / cnt, "launches": cnt}
@@ -117,6 +120,27 @@ def main():
         ctx.profile(False)
         results[kind] = {"ms_per_step": ms, "GBps": bytes_step / (ms * 1e-3) / 1e9, "kernels": kern}
         sk.release()
+
+    # library FP64 GEMM (rocBLAS through torch) on the same shapes, for the
+    # "faster of the two" FP64 Gaussian baseline; R drawn by torch (timing only)
+    Rt = torch.randn(n, d, dtype=torch.float64, device="cuda")
+    At_row = A.T  # row-major view of the column-major A
+    def dgemm(i):
+        torch.mm(A, Rt)
+        torch.mm(At_row, Rt)
+    lib_ms = time_steps(dgemm, max(3, args.steps // 2), 1)
+    del Rt
+    g64 = results.get("gaussian", {})
+    base_ms = min([x for x in (g64.get("ms_per_step"), lib_ms) if x])
+    for kind in ("sjlt", "srht"):
+        if "ms_per_step" in results.get(kind, {}):
+            results[kind]["speedup_vs_fp64_gaussian"] = round(base_ms / results[kind]["ms_per_step"], 3)
+    if "ms_per_step" in g64:
+        flops = 2 * 2 * n * n * d
+        g64["TFLOPs"] = round(flops / (g64["ms_per_step"] * 1e-3) / 1e12, 2)
+        g64["frac_fp64_peak"] = round(g64["TFLOPs"] / FP64_PEAK_TFLOPS, 4)
+    results["fp64_gemm_library_ms"] = round(lib_ms, 4)
+    results["fp64_gaussian_baseline_ms"] = round(base_ms, 4)
 
     main_kind = "sjlt"
     r = results[main_kind]

@@ -126,6 +126,22 @@ int sketch_extend(sk_handle *h, const sk_input *in, int32_t dd, int32_t nblocks,
  * handle exists.  out holds all d columns.  Asynchronous. */
 int sketch_rerun(sk_handle *h, const sk_input *in, uint64_t seed, const sk_output *out, void *stream);
 
+/* sketch_adjoint: backward of the sketch for the operator blocks
+ * [block0, block0 + nblocks) (their columns, in order, are the columns of dS).
+ *   DENSE (SJLT): dA = dS R^T (the adjoint of A -> A R), m x n, overwritten;
+ *                 dS is m x (sum of the blocks' widths), lddS >= m, lddA >= m.
+ *   POINTS (SJLT): with dS = W = dL/dS for S = K(X, h) R, writes
+ *                 dX = dL/dX (N x dim row-major, FP32, device) and
+ *                 *dh = dL/dh (one FP64 value, device), K recomputed tile by tile:
+ *                 dL/dx_i = -(1/h^2) sum_j (G_ij + G_ji) K_ij (x_i - x_j),
+ *                 dL/dh = sum_ij G_ij K_ij |x_i - x_j|^2 / h^3, G = W R^T.
+ *                 Requires nblocks * alpha <= 16 and at most 256 columns.
+ * The input must be the one the handle was applied to.  Asynchronous; uses the
+ * context workspace (calls sharing a context must be ordered on one stream).
+ * Errors: SK_EINVAL, SK_EUNSUPPORTED (other operator kinds), SK_ENOMEM, SK_EHIP. */
+int sketch_adjoint(sk_handle *h, const sk_input *in, int32_t block0, int32_t nblocks, const void *dS, int64_t lddS,
+                   void *dA, int64_t lddA, float *dX, double *dh, void *stream);
+
 /* sketch_width: current total width d and number of blocks of the operator. */
 int sketch_width(const sk_handle *h, int32_t *d, int32_t *nblocks);
 

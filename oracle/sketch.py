@@ -119,6 +119,32 @@ def kernel_grad(X, h, R, W, block_rows=1024):
     return dX, dh
 
 
+def kernel_grad_rows(X, h, R, W, rows):
+    """dL/dx_i of L = sum(W o (K R)) for the listed rows i only (same closed
+    form as ``kernel_grad``), O(len(rows) N) work."""
+    X = np.asarray(X, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    out = np.zeros((len(rows), X.shape[1]))
+    for t, i in enumerate(rows):
+        diff = X[i][None, :] - X                      # (N, dim)
+        K = np.exp(-(diff ** 2).sum(1) / (2.0 * h * h))
+        Gi = R @ W[i]                                 # G_ij over j
+        Gti = W @ R[i]                                # G_ji over j
+        out[t] = -(((Gi + Gti) * K)[:, None] * diff).sum(0) / (h * h)
+    return out
+
+
+def kernel_sketch_rows(X, h, R, rows, shift=0.0):
+    """Rows i of S = K(X, h) R (plus shift R(i, :)) in FP64."""
+    X = np.asarray(X, dtype=np.float64)
+    out = np.zeros((len(rows), R.shape[1]))
+    for t, i in enumerate(rows):
+        K = np.exp(-((X[i][None, :] - X) ** 2).sum(1) / (2.0 * h * h))
+        out[t] = K @ R + shift * R[i]
+    return out
+
+
 def finite_difference_grad(X, h, R, W, coords, step=1e-4):
     """Central finite differences of L = sum(W o (K(X,h) R)) in FP64.
 

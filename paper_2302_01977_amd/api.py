@@ -151,6 +151,7 @@ class Sketch:
         _check(self._lib.sketch_apply(ctx.ptr, ctypes.byref(self._in), ctypes.byref(op), d, seed,
                                       ctypes.byref(_output(self.S, self.St)), ctypes.byref(self.h),
                                       _stream(stream)))
+        self.widths = [d]
         ctx._live.add(self)
 
     # -------------------------------------------------------------- growth
@@ -162,6 +163,7 @@ class Sketch:
         Stn = colmajor(self._in.n, w, self.dtype, self.device) if self.transpose else None
         _check(self._lib.sketch_extend(self.h, ctypes.byref(self._in), dd, nblocks,
                                        ctypes.byref(_output(Sn, Stn)), _stream(stream)))
+        self.widths += [dd] * nblocks
         self.S = _hcat(self.S, Sn)
         if self.transpose:
             self.St = _hcat(self.St, Stn)
@@ -171,6 +173,33 @@ class Sketch:
         """Redraw every block from ``seed`` and recompute all columns in place."""
         _check(self._lib.sketch_rerun(self.h, ctypes.byref(self._in), seed,
                                       ctypes.byref(_output(self.S, self.St)), _stream(stream)))
+
+    # -------------------------------------------------------------- backward
+    def adjoint(self, dS, block0=0, nblocks=None, stream=None):
+        """Backward of the sketch for blocks [block0, block0 + nblocks).
+
+        Stored A: returns dA = dS R^T (m x n, column-major).
+        Point input: dS is W = dL/dS; returns (dX, dh) for L = sum(W o S)."""
+        nb = len(self.widths) - block0 if nblocks is None else nblocks
+        if not (0 <= block0 and 1 <= nb and block0 + nb <= len(self.widths)):
+            raise ValueError("block range [%d, %d) outside the %d blocks" % (block0, block0 + nb, len(self.widths)))
+        wt = sum(self.widths[block0:block0 + nb])
+        if tuple(dS.shape) != (self.rows, wt) or dS.dtype != self.dtype or dS.device != self.device:
+            raise ValueError("dS must be a %d x %d %s tensor on %s, got %s %s on %s"
+                             % (self.rows, wt, self.dtype, self.device, tuple(dS.shape), dS.dtype, dS.device))
+        dS = _as_colmajor(dS)
+        dS_ld = _ld(dS)
+        if self._in.input == abi.SK_POINTS:
+            X = self._keep
+            dX = torch.empty_like(X)
+            dh = torch.empty((), dtype=torch.float64, device=X.device)
+            _check(self._lib.sketch_adjoint(self.h, ctypes.byref(self._in), block0, nb, dS.data_ptr(), dS_ld,
+                                            None, 0, dX.data_ptr(), dh.data_ptr(), _stream(stream)))
+            return dX, dh
+        dA = colmajor(self._in.m, self._in.n, self.dtype, self.device)
+        _check(self._lib.sketch_adjoint(self.h, ctypes.byref(self._in), block0, nb, dS.data_ptr(), dS_ld,
+                                        dA.data_ptr(), _ld(dA), None, None, _stream(stream)))
+        return dA
 
     # -------------------------------------------------------------- queries
     @property
@@ -213,6 +242,56 @@ class Sketch:
             self.release()
         except Exception:
             pass
+
+
+def _as_colmajor(T):
+    if T.dim() == 2 and (T.stride(0) == 1 or T.shape[0] == 1):
+        return T
+    return T.t().contiguous().t()
+
+
+class DenseSketchFn(torch.autograd.Function):
+    """S = A R with a hand-written backward dA = dS R^T (SJLT)."""
+
+    @staticmethod
+    def forward(fctx, A, lib_ctx, d, seed, alpha):
+        sk = Sketch(lib_ctx, _as_colmajor(A.detach()), "sjlt", d, seed, alpha=alpha)
+        fctx.sk = sk
+        return sk.S
+
+    @staticmethod
+    def backward(fctx, gS):
+        dA = fctx.sk.adjoint(gS)
+        return dA, None, None, None, None
+
+
+class KernelSketchFn(torch.autograd.Function):
+    """S = K(X, h) R (SJLT R, K never stored) with the hand-written backward
+    for dL/dX and dL/dh; the bandwidth h is a 0-dim tensor."""
+
+    @staticmethod
+    def forward(fctx, X, h, lib_ctx, d, seed, alpha, shift):
+        X = X.detach().contiguous()
+        sk = Sketch(lib_ctx, None, "sjlt", d, seed, alpha=alpha, points=(X, float(h), shift))
+        fctx.sk = sk
+        fctx.h_dtype = h.dtype if torch.is_tensor(h) else None
+        return sk.S
+
+    @staticmethod
+    def backward(fctx, gS):
+        dX, dh = fctx.sk.adjoint(gS)
+        dh = dh.to(fctx.h_dtype) if fctx.h_dtype is not None else None
+        return dX, dh, None, None, None, None, None
+
+
+def kernel_sketch(X, h, d, seed, lib_ctx, alpha=4, shift=0.0):
+    """Differentiable matrix-free sketch S = K(X, h) R."""
+    return KernelSketchFn.apply(X, h, lib_ctx, d, seed, alpha, shift)
+
+
+def dense_sketch(A, d, seed, lib_ctx, alpha=4):
+    """Differentiable SJLT sketch S = A R of a stored matrix."""
+    return DenseSketchFn.apply(A, lib_ctx, d, seed, alpha)
 
 
 def _hcat(X, Y):

@@ -164,8 +164,7 @@ static int add_block(Handle* h, int32_t w) {
     const int64_t nT = (h->n + h->kc - 1) / h->kc;
     if (!rc) rc = dev_alloc(&b.codes, (size_t)h->n * h->alpha);
     if (!rc) rc = dev_alloc(&b.ptr, (size_t)nT * (w + 1));
-    // +8: the gather fetches bucket entries eight at a time (the excess is unused)
-    if (!rc) rc = dev_alloc(&b.ent, (size_t)h->n * h->alpha + 8);
+    if (!rc) rc = dev_alloc(&b.ent, (size_t)h->n * h->alpha);
   } else if (h->kind == SK_GAUSSIAN) {
     if (!rc) rc = dev_alloc(&b.gbf, (size_t)h->n * w);
   } else if (h->kind == SK_SRHT) {
@@ -206,8 +205,7 @@ static int compute_pass(Handle* h, const sk_input* in, int b0, int b1, const sk_
     if (!rc && out->St) rc = pass(h, in, b0, b1, true, out->St, out->ldSt, st);
     return rc;
   }
-  set_error("operator kind %d with input kind %d is not available in this build", h->kind, in->input);
-  return SK_EUNSUPPORTED;
+  return launch_mf_pass(h, in, b0, b1, out->S, out->ldS, st);
 }
 
 // split a run of blocks into passes of at most MAX_PASS_BLOCKS blocks
@@ -321,6 +319,8 @@ int sketch_apply(sk_ctx* ctx, const sk_input* in, const sk_op_desc* op, int32_t 
   if (op->kind == SK_SRHT)
     SK_REQUIRE(is_pow2(op_rows(in)), SK_EUNSUPPORTED, "SRHT needs n a power of two (got %lld)",
                (long long)op_rows(in));
+  if (in->input == SK_POINTS)
+    SK_REQUIRE(op->kind == SK_SJLT, SK_EUNSUPPORTED, "the matrix-free kernel sketch uses the SJLT operator");
   SK_REQUIRE(op->prec >= SK_PREC_NATIVE && op->prec <= SK_PREC_BF16X3, SK_EINVAL, "unknown precision %d", op->prec);
   if (op->kind == SK_GAUSSIAN && op->prec != SK_PREC_NATIVE)
     SK_REQUIRE(in->dtype == SK_F32, SK_EINVAL, "bf16 Gaussian arithmetic needs FP32 A");
@@ -397,6 +397,28 @@ int sketch_rerun(sk_handle* H, const sk_input* in, uint64_t seed, const sk_outpu
   for (int b = 0; b < (int)h->blocks.size(); ++b)
     if (int rc = gen_block(h, b, st)) return rc;
   return compute_blocks(h, in, 0, (int)h->blocks.size(), out, st);
+}
+
+int sketch_adjoint(sk_handle* H, const sk_input* in, int32_t block0, int32_t nblocks, const void* dS, int64_t lddS,
+                   void* dA, int64_t lddA, float* dX, double* dh, void* stream) {
+  if (int rc = check_handle(H)) return rc;
+  Handle* h = &H->h;
+  if (int rc = validate_input(in)) return rc;
+  if (int rc = check_same_input(h, in)) return rc;
+  SK_REQUIRE(nblocks >= 1 && block0 >= 0 && block0 + nblocks <= (int)h->blocks.size(), SK_EINVAL,
+             "block range [%d, %d) outside the operator's %d blocks", block0, block0 + nblocks,
+             (int)h->blocks.size());
+  SK_REQUIRE(dS, SK_EINVAL, "dS is NULL");
+  const int64_t rows = in->input == SK_POINTS ? in->N : in->m;
+  SK_REQUIRE(lddS >= rows, SK_EINVAL, "lddS < rows");
+  SK_HIP(hipSetDevice(h->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  if (in->input == SK_DENSE) {
+    SK_REQUIRE(dA && lddA >= in->m, SK_EINVAL, "dA is NULL or lddA < m");
+    return launch_sjlt_adjoint(h, in, block0, block0 + nblocks, dS, lddS, dA, lddA, st);
+  }
+  SK_REQUIRE(dX && dh, SK_EINVAL, "dX and dh are required for point input");
+  return launch_mf_backward(h, in, block0, block0 + nblocks, (const float*)dS, lddS, dX, dh, st);
 }
 
 int sketch_width(const sk_handle* H, int32_t* d, int32_t* nblocks) {

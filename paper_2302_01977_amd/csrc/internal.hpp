@@ -116,6 +116,13 @@ int launch_srht_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
                      hipStream_t st);
 int launch_gauss_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, void* out, int64_t ldo,
                       hipStream_t st);
+int launch_mf_pass(Handle* h, const sk_input* in, int b0, int b1, void* out, int64_t ldo, hipStream_t st);
+int launch_mf_backward(Handle* h, const sk_input* in, int b0, int b1, const float* W, int64_t ldw, float* dX,
+                       double* dh, hipStream_t st);
+int launch_sjlt_adjoint(Handle* h, const sk_input* in, int b0, int b1, const void* dS, int64_t lddS, void* dA,
+                        int64_t lddA, hipStream_t st);
+void split_reduce_f32(const float* part, int split, int64_t L, int64_t W, float* out, int64_t ldo, float scale,
+                      hipStream_t st);
 
 int ensure_work(Ctx* c, size_t bytes);
 int sjlt_chunk_for(int w, int alpha);

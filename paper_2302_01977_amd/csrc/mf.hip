@@ -1,0 +1,369 @@
+// Matrix-free Gaussian-kernel sketch S = K(X, h) R with an SJLT R, and its
+// hand-written backward.  K_ij = exp(-|x_i - x_j|^2 / (2 h^2)) (+ shift on the
+// diagonal) is never stored: every kernel recomputes the tiles it needs.
+// (The paper's construction is only partially matrix-free, section 2.2; here the
+// sketch itself is.)
+//
+// Forward: the stored-A SJLT gather with the LDS tile produced in registers:
+// a workgroup owns 64 points i (lanes) and, per chunk of KC source points k,
+// each wave evaluates K_ik for a slice of the chunk; the bucket gather then adds
+// the signed entries exactly as for a stored matrix.
+//
+// Backward for L = sum(W o S) (W = dL/dS): with G = W R^T,
+//   dL/dx_i = -(1/h^2) sum_j (G_ij + G_ji) K_ij (x_i - x_j),
+//   dL/dh   =  sum_ij G_ij K_ij |x_i - x_j|^2 / h^3.
+// G_ij = sum_c sign(j,c) W(i, col(j,c)) / sqrt(alpha) reads the columns named by
+// the (uniform) hash of j from an LDS copy of W's rows i; G_ji reads row j of W
+// at the columns named by the hash of lane i, from a row-major copy of W (a
+// 1 KB row shared by the whole wave).  Pair terms are summed in FP32 over a
+// chunk of sources and in FP64 across chunks; waves and workgroups are combined
+// in a fixed order, so the result is deterministic.
+#include <algorithm>
+
+#include "gather.hpp"
+#include "internal.hpp"
+
+namespace sk {
+
+template <int NW, int NJ, int KCK, int DIM>
+__global__ void __launch_bounds__(NW * 64)
+    mf_sjlt_kernel(const float* __restrict__ X, int64_t N, float c2, float shift, SjltPass pass,
+                   float* __restrict__ out, int64_t ldo, float scale, int split, float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) float tile[KCK * 64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t l0 = (int64_t)blockIdx.x * 64;
+  const int64_t i = l0 + lane;
+  const int s = blockIdx.y;
+  const int nT = pass.nT;
+  const int t0 = (int)(((int64_t)nT * s) / split);
+  const int t1 = (int)(((int64_t)nT * (s + 1)) / split);
+  const int g = blockIdx.z * NW + wave;
+  const bool active = g < pass.ngroups;
+  const int blk = active ? pass.grp_blk[g] : 0;
+  const int jb = active ? pass.grp_col[g] : 0;
+  const int64_t prow = pass.wtot[blk] + 1;
+  const int32_t* __restrict__ ptr = pass.ptr[blk] + jb;
+  const int32_t* __restrict__ ent = pass.ent[blk];
+
+  float xi[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) xi[d] = i < N ? X[i * DIM + d] : 0.f;
+
+  float acc[NJ][1];
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) acc[jj][0] = 0.f;
+  const uint32_t lane_off = (uint32_t)lane * 4u;
+  const char* tbase = (const char*)tile;
+  auto LD = [&](int v) -> float { return *(const float*)(tbase + ((uint32_t)v >> 1) * 256u + lane_off); };
+
+  for (int t = t0; t < t1; ++t) {
+    const int64_t k0 = (int64_t)t * KCK;
+    __syncthreads();  // previous chunk consumed
+#pragma unroll 4
+    for (int src = wave; src < KCK; src += NW) {
+      const int64_t k = k0 + src;
+      float v = 0.f;
+      if (k < N) {
+        float d2 = 0.f;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const float df = xi[d] - X[k * DIM + d];
+          d2 = fmaf(df, df, d2);
+        }
+        v = __builtin_amdgcn_exp2f(-d2 * c2);
+        if (k == i) v += shift;
+      }
+      tile[src * 64 + lane] = v;
+    }
+    __syncthreads();
+    if (active) gather_chunk<float, NJ, 1, float>(ptr + (int64_t)t * prow, ent, LD, acc);
+  }
+  if (!active || i >= N) return;
+  const int64_t jc = (int64_t)g * NJ;
+  if (split == 1) {
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) out[i + (jc + jj) * ldo] = acc[jj][0] * scale;
+  } else {
+    float* p = part + (int64_t)s * N * ((int64_t)pass.ngroups * NJ);
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) p[i + (jc + jj) * N] = acc[jj][0];
+  }
+}
+
+// ----------------------------------------------------------------- backward
+struct MfBlocks {
+  const uint32_t* codes[MAX_PASS_BLOCKS];  // per block: n * alpha hash codes
+  int32_t coloff[MAX_PASS_BLOCKS];         // first column of the block inside W
+  int32_t nb;
+};
+
+// row-major copy of the column-major N x w matrix W (tiled transpose)
+__global__ void __launch_bounds__(256) transpose_kernel(const float* __restrict__ W, int64_t ldw, int64_t N, int w,
+                                                        float* __restrict__ Wrm) {
+  __shared__ float t[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32;
+  const int c0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t r = r0 + tx;
+    const int c = c0 + y;
+    t[y][tx] = (r < N && c < w) ? W[r + (int64_t)c * ldw] : 0.f;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t r = r0 + y;
+    const int c = c0 + tx;
+    if (r < N && c < w) Wrm[r * w + c] = t[tx][y];
+  }
+}
+
+template <int DIM, int NWB, int KCB, int MAXA>
+__global__ void __launch_bounds__(NWB * 64)
+    mf_bwd_kernel(const float* __restrict__ X, int64_t N, float c2, const float* __restrict__ W, int64_t ldw,
+                  const float* __restrict__ Wrm, int Wt, MfBlocks mb, int alpha, float* __restrict__ dX,
+                  float xscale, double* __restrict__ dh_part) {
+  __shared__ __attribute__((aligned(16))) float Wr[256 * 64];  // Wr[col * 64 + lane] = W(l0 + lane, col), col < Wt
+  __shared__ double red[NWB][DIM + 1][64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t l0 = (int64_t)blockIdx.x * 64;
+  const int64_t i = l0 + lane;
+  const bool lane_ok = i < N;
+
+  for (int e = tid; e < Wt * 64; e += NWB * 64) {
+    const int col = e >> 6, r = e & 63;
+    Wr[e] = (l0 + r < N) ? W[(l0 + r) + (int64_t)col * ldw] : 0.f;
+  }
+  float xi[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) xi[d] = lane_ok ? X[i * DIM + d] : 0.f;
+  // this lane's own hash columns and signs (for G_ji)
+  int colL[MAXA];
+  float sgL[MAXA];
+  const int na = mb.nb * alpha;
+#pragma unroll
+  for (int q = 0; q < MAXA; ++q) {
+    colL[q] = 0;
+    sgL[q] = 0.f;
+    if (q < na && lane_ok) {
+      const int b = q / alpha, c = q % alpha;
+      const uint32_t code = mb.codes[b][i * alpha + c];
+      colL[q] = (int)(code >> 1) + mb.coloff[b];
+      sgL[q] = (code & 1u) ? -1.f : 1.f;
+    }
+  }
+  __syncthreads();
+
+  double ax[DIM], ah = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) ax[d] = 0.0;
+  for (int64_t j0 = (int64_t)wave * KCB; j0 < N; j0 += (int64_t)NWB * KCB) {
+    float px[DIM], ph = 0.f;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) px[d] = 0.f;
+    const int jn = (int)std::min<int64_t>(KCB, N - j0);
+#pragma unroll 2
+    for (int jj = 0; jj < jn; ++jj) {
+      const int64_t j = j0 + jj;
+      float df[DIM], r2 = 0.f;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        df[d] = xi[d] - X[j * DIM + d];
+        r2 = fmaf(df[d], df[d], r2);
+      }
+      const float K = __builtin_amdgcn_exp2f(-r2 * c2);
+      float gij = 0.f, gji = 0.f;
+      const float* __restrict__ wrow = Wrm + j * Wt;
+#pragma unroll
+      for (int q = 0; q < MAXA; ++q) {
+        if (q < na) {
+          const int b = q / alpha, c = q % alpha;
+          const uint32_t code = mb.codes[b][j * alpha + c];
+          const float sg = __builtin_bit_cast(float, (code << 31) | 0x3f800000u);
+          gij = fmaf(Wr[((int)(code >> 1) + mb.coloff[b]) * 64 + lane], sg, gij);
+          gji = fmaf(wrow[colL[q]], sgL[q], gji);
+        }
+      }
+      const float M = (gij + gji) * K;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) px[d] = fmaf(M, df[d], px[d]);
+      ph = fmaf(gij * K, r2, ph);
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ax[d] += (double)px[d];
+    ah += (double)ph;
+  }
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) red[wave][d][lane] = ax[d];
+  red[wave][DIM][lane] = lane_ok ? ah : 0.0;
+  __syncthreads();
+  if (wave == 0) {
+    double sx[DIM], sh = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) sx[d] = 0.0;
+    for (int q = 0; q < NWB; ++q) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) sx[d] += red[q][d][lane];
+      sh += red[q][DIM][lane];
+    }
+    if (lane_ok) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) dX[i * DIM + d] = (float)(sx[d] * (double)xscale);
+    }
+    red[0][DIM][lane] = sh;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int l = 0; l < 64; ++l) t += red[0][DIM][l];
+    dh_part[blockIdx.x] = t;
+  }
+}
+
+__global__ void dh_reduce_kernel(const double* __restrict__ part, int64_t np, double scale, double* __restrict__ dh) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double t = 0.0;
+  for (int64_t q = 0; q < np; ++q) t += part[q];
+  *dh = t * scale;
+}
+
+// ------------------------------------------------------------------ launch
+template <int NW, int NJ, int KCK>
+static int run_mf(Ctx* c, int dim, const float* X, int64_t N, float c2, float shift, const SjltPass& pass,
+                  float* out, int64_t ldo, float scale, int split, float* part, int gz, hipStream_t st) {
+  dim3 grid((unsigned)((N + 63) / 64), (unsigned)split, (unsigned)gz);
+  ProfScope ps(c, "mf_fwd", st);
+  switch (dim) {
+    case 1: mf_sjlt_kernel<NW, NJ, KCK, 1><<<grid, NW * 64, 0, st>>>(X, N, c2, shift, pass, out, ldo, scale, split, part); break;
+    case 2: mf_sjlt_kernel<NW, NJ, KCK, 2><<<grid, NW * 64, 0, st>>>(X, N, c2, shift, pass, out, ldo, scale, split, part); break;
+    case 3: mf_sjlt_kernel<NW, NJ, KCK, 3><<<grid, NW * 64, 0, st>>>(X, N, c2, shift, pass, out, ldo, scale, split, part); break;
+    default: mf_sjlt_kernel<NW, NJ, KCK, 4><<<grid, NW * 64, 0, st>>>(X, N, c2, shift, pass, out, ldo, scale, split, part); break;
+  }
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+static constexpr double LOG2E = 1.4426950408889634;
+
+int launch_mf_pass(Handle* h, const sk_input* in, int b0, int b1, void* out, int64_t ldo, hipStream_t st) {
+  SK_REQUIRE(h->kind == SK_SJLT, SK_EUNSUPPORTED, "the matrix-free kernel sketch uses the SJLT operator");
+  const int nblk = b1 - b0;
+  SK_REQUIRE(nblk >= 1 && nblk <= MAX_PASS_BLOCKS, SK_EINVAL, "a pass covers 1..%d blocks", MAX_PASS_BLOCKS);
+  int W = 0, g = 0;
+  for (int b = b0; b < b1; ++b) {
+    W += h->blocks[b].w;
+    int a = g, bb = h->blocks[b].w;
+    while (bb) {
+      const int t = a % bb;
+      a = bb;
+      bb = t;
+    }
+    g = a;
+  }
+  const int nj = (g % 32 == 0 && W >= 128) ? 32 : 16;
+  const int ngroups = W / nj;
+  SK_REQUIRE(ngroups <= MAX_PASS_GROUPS, SK_EINVAL, "pass too wide (%d columns)", W);
+  const int nw = ngroups <= 4 ? 4 : 8;
+  const int gz = (ngroups + nw - 1) / nw;
+  SjltPass pass;
+  memset(&pass, 0, sizeof(pass));
+  pass.nT = (int)((h->n + h->kc - 1) / h->kc);
+  pass.ngroups = ngroups;
+  int gi = 0;
+  for (int b = b0; b < b1; ++b) {
+    const Block& B = h->blocks[b];
+    pass.ptr[b - b0] = B.ptr;
+    pass.ent[b - b0] = B.ent;
+    pass.wtot[b - b0] = B.w;
+    for (int c = 0; c < B.w; c += nj) {
+      pass.grp_blk[gi] = b - b0;
+      pass.grp_col[gi] = c;
+      ++gi;
+    }
+  }
+  const int64_t N = in->N;
+  const int64_t tiles = ((N + 63) / 64) * gz;
+  const size_t tile_bytes = (size_t)h->kc * 64 * 4;
+  const int64_t per_cu = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)tile_bytes);
+  const int64_t target = per_cu * (int64_t)h->ctx->num_cu;
+  int split = 1;
+  if (tiles < target) split = (int)std::min<int64_t>((target + tiles - 1) / tiles, std::max(1, pass.nT / 4));
+  float* part = nullptr;
+  if (split > 1) {
+    if (int rc = ensure_work(h->ctx, (size_t)split * (size_t)N * (size_t)W * 4)) return rc;
+    part = (float*)h->ctx->work;
+  }
+  const float c2 = (float)(LOG2E / (2.0 * (double)in->h * (double)in->h));
+  const float scale = (float)(1.0 / sqrt((double)h->alpha));
+  int rc = SK_EINVAL;
+  const int kc = h->kc;
+#define SK_MF(NW_, NJ_, KC_) \
+  if (nw == NW_ && nj == NJ_ && kc == KC_) rc = run_mf<NW_, NJ_, KC_>(h->ctx, in->dim, in->X, N, c2, in->shift, pass, (float*)out, ldo, scale, split, part, gz, st); else
+  SK_MF(4, 16, 64) SK_MF(8, 16, 64) SK_MF(4, 32, 64) SK_MF(8, 32, 64)
+  SK_MF(4, 16, 128) SK_MF(8, 16, 128) SK_MF(4, 32, 128) SK_MF(8, 32, 128)
+  SK_MF(4, 16, 256) SK_MF(8, 16, 256) SK_MF(4, 32, 256) SK_MF(8, 32, 256) {
+    set_error("internal: no matrix-free kernel for NW=%d NJ=%d KC=%d", nw, nj, kc);
+  }
+#undef SK_MF
+  if (rc) return rc;
+  if (split > 1) {
+    ProfScope ps(h->ctx, "sjlt_reduce", st);
+    split_reduce_f32(part, split, N, W, (float*)out, ldo, scale, st);
+    SK_HIP(hipGetLastError());
+  }
+  return SK_OK;
+}
+
+int launch_mf_backward(Handle* h, const sk_input* in, int b0, int b1, const float* Wd, int64_t ldw, float* dX,
+                       double* dh, hipStream_t st) {
+  SK_REQUIRE(h->kind == SK_SJLT, SK_EUNSUPPORTED, "the matrix-free backward uses the SJLT operator");
+  const int nblk = b1 - b0;
+  SK_REQUIRE(nblk >= 1 && nblk <= MAX_PASS_BLOCKS, SK_EINVAL, "the backward covers 1..%d blocks", MAX_PASS_BLOCKS);
+  SK_REQUIRE(nblk * h->alpha <= 16, SK_EUNSUPPORTED, "the backward supports nblocks * alpha <= 16");
+  MfBlocks mb;
+  memset(&mb, 0, sizeof(mb));
+  int Wt = 0;
+  for (int b = b0; b < b1; ++b) {
+    mb.codes[b - b0] = h->blocks[b].codes;
+    mb.coloff[b - b0] = Wt;
+    Wt += h->blocks[b].w;
+  }
+  mb.nb = nblk;
+  SK_REQUIRE(Wt <= 256, SK_EUNSUPPORTED, "the backward supports at most 256 sketch columns per call");
+  const int64_t N = in->N;
+  const int64_t nwg = (N + 63) / 64;
+  // workspace: row-major copy of W, then per-workgroup dh partials
+  const size_t wrm_bytes = ((size_t)N * Wt * 4 + 255) & ~(size_t)255;
+  if (int rc = ensure_work(h->ctx, wrm_bytes + (size_t)nwg * 8)) return rc;
+  float* Wrm = (float*)h->ctx->work;
+  double* dh_part = (double*)((char*)h->ctx->work + wrm_bytes);
+  {
+    dim3 grid((unsigned)((N + 31) / 32), (unsigned)((Wt + 31) / 32));
+    transpose_kernel<<<grid, 256, 0, st>>>(Wd, ldw, N, Wt, Wrm);
+    SK_HIP(hipGetLastError());
+  }
+  const double hh = (double)in->h;
+  const float c2 = (float)(LOG2E / (2.0 * hh * hh));
+  const double ga = 1.0 / sqrt((double)h->alpha);
+  const float xscale = (float)(-ga / (hh * hh));
+  constexpr int NWB = 4, KCB = 32;
+  {
+    ProfScope ps(h->ctx, "mf_bwd", st);
+    const dim3 grid((unsigned)nwg);
+    switch (in->dim) {
+      case 1: mf_bwd_kernel<1, NWB, KCB, 16><<<grid, NWB * 64, 0, st>>>(in->X, N, c2, Wd, ldw, Wrm, Wt, mb, h->alpha, dX, xscale, dh_part); break;
+      case 2: mf_bwd_kernel<2, NWB, KCB, 16><<<grid, NWB * 64, 0, st>>>(in->X, N, c2, Wd, ldw, Wrm, Wt, mb, h->alpha, dX, xscale, dh_part); break;
+      case 3: mf_bwd_kernel<3, NWB, KCB, 16><<<grid, NWB * 64, 0, st>>>(in->X, N, c2, Wd, ldw, Wrm, Wt, mb, h->alpha, dX, xscale, dh_part); break;
+      default: mf_bwd_kernel<4, NWB, KCB, 16><<<grid, NWB * 64, 0, st>>>(in->X, N, c2, Wd, ldw, Wrm, Wt, mb, h->alpha, dX, xscale, dh_part); break;
+    }
+    SK_HIP(hipGetLastError());
+  }
+  dh_reduce_kernel<<<1, 64, 0, st>>>(dh_part, nwg, ga / (hh * hh * hh), dh);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+}  // namespace sk

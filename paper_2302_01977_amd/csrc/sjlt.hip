@@ -22,6 +22,7 @@
 // then free of bank conflicts.
 #include <algorithm>
 
+#include "gather.hpp"
 #include "internal.hpp"
 
 namespace sk {
@@ -190,54 +191,13 @@ __global__ void __launch_bounds__(NW * 64)
     return *(const VT*)(tbase + a);
   };
 
-  // +-1 from the entry's sign bit, built with integer operations on the uniform
-  // entry so that it stays a scalar operand of the FMA
-  auto sgn = [](int v) -> T {
-    if constexpr (sizeof(T) == 4) {
-      return __builtin_bit_cast(float, ((uint32_t)v << 31) | 0x3f800000u);
-    } else {
-      return __builtin_bit_cast(double, ((uint64_t)(uint32_t)v << 63) | 0x3ff0000000000000ull);
-    }
-  };
-
   if (t0 < t1) load_chunk(t0);
   for (int t = t0; t < t1; ++t) {
     __syncthreads();  // the previous chunk is fully consumed
     store_chunk();
     __syncthreads();
     if (t + 1 < t1) load_chunk(t + 1);  // in flight during the gather below
-    if (active) {
-      const int32_t* __restrict__ P = ptr + (int64_t)t * prow;
-      int pv[NJ + 1];  // bucket bounds of the wave's columns, loaded once per chunk
-#pragma unroll
-      for (int jj = 0; jj <= NJ; ++jj) pv[jj] = P[jj];
-#pragma unroll
-      for (int jj = 0; jj < NJ; ++jj) {
-        // accumulate straight into acc: separate partial sums per column get
-        // sunk to the end of the chunk by the compiler and inflate VGPR use
-        const int p1 = pv[jj + 1];
-        // up to eight entries per scalar load; all their LDS reads are issued
-        // before the first wait (entries past the bucket end are never used;
-        // the entry array carries 8 slots of padding)
-        for (int e = pv[jj]; e < p1; e += 8) {
-          const int rem = p1 - e;
-          int v[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) v[u] = ent[e + u];
-          VT x[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (u < rem) x[u] = LD(v[u]);
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (u < rem) {
-              const T sg = sgn(v[u]);
-#pragma unroll
-              for (int r = 0; r < RPL; ++r) acc[jj][r] = fma(((const T*)&x[u])[r], sg, acc[jj][r]);
-            }
-        }
-      }
-    }
+    if (active) gather_chunk<T, NJ, RPL, VT>(ptr + (int64_t)t * prow, ent, LD, acc);
   }
 
   if (!active) return;
@@ -268,6 +228,12 @@ __global__ void __launch_bounds__(256) split_reduce_kernel(const T* __restrict__
   T a = T(0);
   for (int s = 0; s < split; ++s) a += part[(int64_t)s * L * W + idx];
   out[row + j * ldo] = a * scale;
+}
+
+void split_reduce_f32(const float* part, int split, int64_t L, int64_t W, float* out, int64_t ldo, float scale,
+                      hipStream_t st) {
+  const int64_t tot = L * W;
+  split_reduce_kernel<float><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(part, split, L, W, out, ldo, scale);
 }
 
 // ------------------------------------------------------------------ dispatch

@@ -1,0 +1,154 @@
+"""GPU parity of the matrix-free kernel sketch, its backward (dL/dX, dL/dh) and
+the stored-A SJLT adjoint, against the FP64 oracle and finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import operators as ops
+from oracle import sketch as osk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2302_01977_amd import api
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _api():
+    from paper_2302_01977_amd import api
+    return api
+
+
+def _points(N, dim, seed):
+    return workloads.uniform_points(N, dim, seed).astype(np.float32)
+
+
+@pytest.mark.parametrize("N,dim,d,alpha,h,shift", [(2000, 3, 64, 4, 0.3, 0.0), (1500, 2, 256, 4, 0.5, 1e-3),
+                                                   (777, 3, 48, 8, 0.2, 0.0), (4096, 1, 32, 4, 0.1, 0.0)])
+def test_forward_parity(ctx, N, dim, d, alpha, h, shift):
+    api = _api()
+    X = _points(N, dim, 3)
+    sk = api.Sketch(ctx, None, "sjlt", d, 9, alpha=alpha, points=(torch.from_numpy(X).cuda(), h, shift))
+    torch.cuda.synchronize()
+    R = ops.sjlt_block(N, d, alpha, 0, 9)
+    ref = osk.kernel_sketch(X.astype(np.float64), h, R, shift=shift)
+    assert osk.rel_fro(sk.S.cpu().numpy(), ref) <= 1e-5
+    sk.release()
+
+
+@pytest.mark.parametrize("N,dim,d,alpha", [(2048, 3, 256, 4), (1000, 2, 64, 8), (333, 3, 32, 4)])
+def test_backward_matches_fp64_reference(ctx, N, dim, d, alpha):
+    api = _api()
+    X = _points(N, dim, 5)
+    h = 0.3
+    W = workloads.random_dense(N, d, 6, np.float32)
+    sk = api.Sketch(ctx, None, "sjlt", d, 12, alpha=alpha, points=(torch.from_numpy(X).cuda(), h, 0.0))
+    dX, dh = sk.adjoint(api.to_device_colmajor(W))
+    torch.cuda.synchronize()
+    R = ops.sjlt_block(N, d, alpha, 0, 12)
+    rX, rh = osk.kernel_grad(X.astype(np.float64), h, R, W.astype(np.float64))
+    ex = osk.rel_fro(dX.cpu().numpy(), rX)
+    eh = abs(float(dh.cpu()) - rh) / abs(rh)
+    print("backward N=%d rel.err dX %.2e dh %.2e" % (N, ex, eh))
+    assert ex <= 1e-6 and eh <= 1e-6
+    sk.release()
+
+
+def test_gradient_against_central_differences(ctx):
+    """The n = 2048 subset of the N = 32768 point set: GPU gradient against FP64
+    central differences (step 1e-4) of the FP64 loss, for dh and 24 coordinates."""
+    api = _api()
+    c = workloads.cfg5()
+    n = 2048
+    X = c["X"][:n]
+    W = np.asarray(c["W"][:n, :64])
+    h = c["h"]
+    sk = api.Sketch(ctx, None, "sjlt", 64, c["seed"], alpha=4, points=(torch.from_numpy(X).cuda(), h, 0.0))
+    dX, dh = sk.adjoint(api.to_device_colmajor(W))
+    torch.cuda.synchronize()
+    R = ops.sjlt_block(n, 64, 4, 0, c["seed"])
+    g = np.random.Generator(np.random.PCG64(7))
+    coords = [(int(i), int(a)) for i, a in zip(g.integers(0, n, 24), g.integers(0, 3, 24))]
+    fd, fdh = osk.finite_difference_grad(X.astype(np.float64), h, R, W.astype(np.float64), coords, step=1e-4)
+    got = np.array([float(dX[i, a]) for i, a in coords])
+    scale = np.abs(fd).max()
+    assert np.abs(got - fd).max() <= 1e-5 * scale
+    assert abs(float(dh.cpu()) - fdh) <= 1e-6 * abs(fdh)
+    sk.release()
+
+
+def test_autograd_function(ctx):
+    api = _api()
+    N, d = 512, 64
+    X = torch.from_numpy(_points(N, 3, 8)).cuda().requires_grad_(True)
+    h = torch.tensor(0.4, dtype=torch.float64, device="cuda", requires_grad=True)
+    W = torch.from_numpy(workloads.random_dense(N, d, 9, np.float32)).cuda()
+    S = api.kernel_sketch(X, h, d, 3, ctx, alpha=4)
+    loss = (W * S).sum()
+    loss.backward()
+    R = ops.sjlt_block(N, d, 4, 0, 3)
+    rX, rh = osk.kernel_grad(X.detach().cpu().numpy().astype(np.float64), 0.4, R,
+                             W.cpu().numpy().astype(np.float64))
+    assert osk.rel_fro(X.grad.cpu().numpy(), rX) <= 1e-6
+    assert abs(float(h.grad) - rh) <= 1e-6 * abs(rh)
+    # dense SJLT sketch through autograd: dA = W R^T
+    A = torch.from_numpy(workloads.random_dense(N, N, 10, np.float64)).cuda().requires_grad_(True)
+    Wd = torch.from_numpy(workloads.random_dense(N, d, 11, np.float64)).cuda()
+    S2 = api.dense_sketch(A, d, 4, ctx, alpha=4)
+    (Wd * S2).sum().backward()
+    R2 = ops.sjlt_block(N, d, 4, 0, 4)
+    assert osk.rel_fro(A.grad.cpu().numpy(), osk.adjoint(Wd.cpu().numpy(), R2)) <= 1e-12
+
+
+def test_full_size_sampled_rows(ctx):
+    """N = 32768 points in [0,1]^3, h = 0.3, SJLT alpha 4, d = 256: 48 seeded rows
+    of S and of dL/dX against the FP64 oracle."""
+    api = _api()
+    c = workloads.cfg5()
+    X, W, h, d = c["X"], np.asarray(c["W"]), c["h"], c["d"]
+    N = X.shape[0]
+    Xd = torch.from_numpy(X).cuda()
+    sk = api.Sketch(ctx, None, "sjlt", d, c["seed"], alpha=4, points=(Xd, h, 0.0))
+    dX, dh = sk.adjoint(api.to_device_colmajor(W))
+    torch.cuda.synchronize()
+    rows = np.sort(np.random.Generator(np.random.PCG64(5)).choice(N, 48, replace=False))
+    R = ops.sjlt_block(N, d, 4, 0, c["seed"])
+    X64 = X.astype(np.float64)
+    refS = osk.kernel_sketch_rows(X64, h, R, rows)
+    assert osk.rel_fro(sk.S[rows].cpu().numpy(), refS) <= 1e-5
+    refX = osk.kernel_grad_rows(X64, h, R, W.astype(np.float64), rows)
+    assert osk.rel_fro(dX[rows].cpu().numpy(), refX) <= 1e-6
+    assert np.isfinite(float(dh.cpu()))
+    sk.release()
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 1e-5)])
+def test_dense_sjlt_adjoint(ctx, dtype, tol):
+    api = _api()
+    m, n = 700, 1000
+    A = workloads.random_dense(m, n, 1, dtype)
+    Ad = api.to_device_colmajor(A)
+    sk = api.Sketch(ctx, Ad, "sjlt", 64, 21, alpha=4)
+    sk.extend(128, nblocks=2)        # 320 columns: two LDS slabs
+    dS = workloads.random_dense(m, 320, 2, dtype)
+    dA = sk.adjoint(api.to_device_colmajor(dS))
+    torch.cuda.synchronize()
+    R = ops.operator("sjlt", n, [64, 128, 128], 21, alpha=4)
+    assert osk.rel_fro(dA.cpu().numpy(), osk.adjoint(dS.astype(np.float64), R)) <= tol
+    # dot test <A R, W> = <A, W R^T> on the device results
+    lhs = float((sk.S.double() * torch.from_numpy(dS).cuda().double()).sum())
+    rhs = float((Ad.double() * dA.double()).sum())
+    assert abs(lhs - rhs) <= 10 * tol * abs(lhs)
+    # a single block
+    dA0 = sk.adjoint(api.to_device_colmajor(dS[:, 64:192]), block0=1, nblocks=1)
+    torch.cuda.synchronize()
+    R1 = ops.sjlt_block(n, 128, 4, 1, 21)
+    assert osk.rel_fro(dA0.cpu().numpy(), osk.adjoint(dS[:, 64:192].astype(np.float64), R1)) <= tol
+    sk.release()
