@@ -15,9 +15,10 @@
 // G_ij = sum_c sign(j,c) W(i, col(j,c)) / sqrt(alpha) reads the columns named by
 // the (uniform) hash of j from an LDS copy of W's rows i; G_ji reads row j of W
 // at the columns named by the hash of lane i, from a row-major copy of W (a
-// 1 KB row shared by the whole wave).  Pair terms are summed in FP32 over a
-// chunk of sources and in FP64 across chunks; waves and workgroups are combined
-// in a fixed order, so the result is deterministic.
+// 1 KB row shared by the whole wave).  dL/dx terms are summed in FP32 over a
+// chunk of sources and in FP64 across chunks; dL/dh, a sum with heavy
+// cancellation, is accumulated in FP64 term by term.  Waves and workgroups are
+// combined in a fixed order, so the result is deterministic.
 #include <algorithm>
 
 #include "gather.hpp"
@@ -161,7 +162,7 @@ __global__ void __launch_bounds__(NWB * 64)
 #pragma unroll
   for (int d = 0; d < DIM; ++d) ax[d] = 0.0;
   for (int64_t j0 = (int64_t)wave * KCB; j0 < N; j0 += (int64_t)NWB * KCB) {
-    float px[DIM], ph = 0.f;
+    float px[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) px[d] = 0.f;
     const int jn = (int)std::min<int64_t>(KCB, N - j0);
@@ -190,11 +191,10 @@ __global__ void __launch_bounds__(NWB * 64)
       const float M = (gij + gji) * K;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) px[d] = fmaf(M, df[d], px[d]);
-      ph = fmaf(gij * K, r2, ph);
+      ah += (double)(gij * K * r2);  // dL/dh cancels heavily: accumulate its terms in FP64
     }
 #pragma unroll
     for (int d = 0; d < DIM; ++d) ax[d] += (double)px[d];
-    ah += (double)ph;
   }
 #pragma unroll
   for (int d = 0; d < DIM; ++d) red[wave][d][lane] = ax[d];

@@ -30,6 +30,11 @@ def _points(N, dim, seed):
     return workloads.uniform_points(N, dim, seed).astype(np.float32)
 
 
+def _f32(x):
+    """The bandwidth as the library receives it (an FP32 value)."""
+    return float(np.float32(x))
+
+
 @pytest.mark.parametrize("N,dim,d,alpha,h,shift", [(2000, 3, 64, 4, 0.3, 0.0), (1500, 2, 256, 4, 0.5, 1e-3),
                                                    (777, 3, 48, 8, 0.2, 0.0), (4096, 1, 32, 4, 0.1, 0.0)])
 def test_forward_parity(ctx, N, dim, d, alpha, h, shift):
@@ -38,7 +43,7 @@ def test_forward_parity(ctx, N, dim, d, alpha, h, shift):
     sk = api.Sketch(ctx, None, "sjlt", d, 9, alpha=alpha, points=(torch.from_numpy(X).cuda(), h, shift))
     torch.cuda.synchronize()
     R = ops.sjlt_block(N, d, alpha, 0, 9)
-    ref = osk.kernel_sketch(X.astype(np.float64), h, R, shift=shift)
+    ref = osk.kernel_sketch(X.astype(np.float64), _f32(h), R, shift=_f32(shift))
     assert osk.rel_fro(sk.S.cpu().numpy(), ref) <= 1e-5
     sk.release()
 
@@ -53,7 +58,7 @@ def test_backward_matches_fp64_reference(ctx, N, dim, d, alpha):
     dX, dh = sk.adjoint(api.to_device_colmajor(W))
     torch.cuda.synchronize()
     R = ops.sjlt_block(N, d, alpha, 0, 12)
-    rX, rh = osk.kernel_grad(X.astype(np.float64), h, R, W.astype(np.float64))
+    rX, rh = osk.kernel_grad(X.astype(np.float64), _f32(h), R, W.astype(np.float64))
     ex = osk.rel_fro(dX.cpu().numpy(), rX)
     eh = abs(float(dh.cpu()) - rh) / abs(rh)
     print("backward N=%d rel.err dX %.2e dh %.2e" % (N, ex, eh))
@@ -76,7 +81,7 @@ def test_gradient_against_central_differences(ctx):
     R = ops.sjlt_block(n, 64, 4, 0, c["seed"])
     g = np.random.Generator(np.random.PCG64(7))
     coords = [(int(i), int(a)) for i, a in zip(g.integers(0, n, 24), g.integers(0, 3, 24))]
-    fd, fdh = osk.finite_difference_grad(X.astype(np.float64), h, R, W.astype(np.float64), coords, step=1e-4)
+    fd, fdh = osk.finite_difference_grad(X.astype(np.float64), _f32(h), R, W.astype(np.float64), coords, step=1e-4)
     got = np.array([float(dX[i, a]) for i, a in coords])
     scale = np.abs(fd).max()
     assert np.abs(got - fd).max() <= 1e-5 * scale
@@ -94,7 +99,7 @@ def test_autograd_function(ctx):
     loss = (W * S).sum()
     loss.backward()
     R = ops.sjlt_block(N, d, 4, 0, 3)
-    rX, rh = osk.kernel_grad(X.detach().cpu().numpy().astype(np.float64), 0.4, R,
+    rX, rh = osk.kernel_grad(X.detach().cpu().numpy().astype(np.float64), _f32(0.4), R,
                              W.cpu().numpy().astype(np.float64))
     assert osk.rel_fro(X.grad.cpu().numpy(), rX) <= 1e-6
     assert abs(float(h.grad) - rh) <= 1e-6 * abs(rh)
@@ -121,9 +126,9 @@ def test_full_size_sampled_rows(ctx):
     rows = np.sort(np.random.Generator(np.random.PCG64(5)).choice(N, 48, replace=False))
     R = ops.sjlt_block(N, d, 4, 0, c["seed"])
     X64 = X.astype(np.float64)
-    refS = osk.kernel_sketch_rows(X64, h, R, rows)
+    refS = osk.kernel_sketch_rows(X64, _f32(h), R, rows)
     assert osk.rel_fro(sk.S[rows].cpu().numpy(), refS) <= 1e-5
-    refX = osk.kernel_grad_rows(X64, h, R, W.astype(np.float64), rows)
+    refX = osk.kernel_grad_rows(X64, _f32(h), R, W.astype(np.float64), rows)
     assert osk.rel_fro(dX[rows].cpu().numpy(), refX) <= 1e-6
     assert np.isfinite(float(dh.cpu()))
     sk.release()
