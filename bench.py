@@ -5,13 +5,23 @@ S = A R and S' = A^T R at d = 256 (one block).  One step = draw the operator
 block on the device (hash + bucket tables) and compute S and S' through the C
 ABI.  The metric is the effective bandwidth of the SJLT sketch (alpha = 4):
 algorithmic bytes (read A once per sketch + write the new columns) divided by the
-step time, with A already resident in HBM.  The other operator kinds available in
-the library are timed on the same input for comparison, and the FP64 CPU oracle
-is timed on the host cores as a reported baseline.
+step time, with A already resident in HBM.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cauchy16k]
+Reported beside it, on the same GPU and in the same run:
+  * the other operator kinds on the same FP64 matrix (SRHT, FP64 Gaussian on
+    MFMA) and the library FP64 GEMM (rocBLAS through torch) on the same shapes;
+  * the same matrix rounded to FP32: SJLT, SRHT, Gaussian in BF16 and bf16x3,
+    each with its relative error against the FP64-arithmetic Gaussian path;
+  * the matrix-free kernel sketch and its backward (N = 32768 points in 3-D,
+    d = 256);
+  * a measured copy bandwidth (torch copy of A), the reference for the HBM
+    counters;
+  * the FP64 CPU oracle timed on the host cores (a reported baseline).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,10 +32,17 @@ sys.path.insert(0, ROOT)
 
 KERNELS = {"sjlt": ("sjlt_gather", "sjlt_gather_t", "sjlt_reduce", "sjlt_meta"),
            "srht": ("srht", "srht_t"),
-           "gaussian": ("gauss_f64", "gauss_f64_t")}
+           "gaussian": ("gauss_f64", "gauss_f64_t"),
+           "bf16": ("gauss_bf16", "gauss_bf16_t"),
+           "bf16x3": ("gauss_bf16x3", "gauss_bf16x3_t")}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 BF16_PEAK_TFLOPS = 2500.0
+# VALU issue without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+# the dominant kernel's sources: the traffic figures below are valid only for them
+GATHER_SOURCES = ("paper_2302_01977_amd/csrc/sjlt.hip", "paper_2302_01977_amd/csrc/gather.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sjlt_gather_cauchy16k_traffic.txt")
 
 
 def parse():
@@ -35,7 +52,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="cauchy16k", choices=["cauchy16k"])
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--kinds", default="sjlt,srht,gaussian")
+    p.add_argument("--only-main", action="store_true", help="time the SJLT step and the copy reference only")
     return p.parse_args()
 
 
@@ -52,6 +69,52 @@ def time_steps(fn, steps, warmup):
     t1.record()
     torch.cuda.synchronize()
     return t0.elapsed_time(t1) / steps
+
+
+def kernel_times(ctx, fn, names, reps):
+    """Average duration per launch of each kernel family, from the HIP events the
+    library records on the stream it launches on."""
+    import torch
+    ctx.profile(True)
+    ctx.profile_read("", reset=True)
+    for i in range(reps):
+        fn(1000 + i)
+    torch.cuda.synchronize()
+    out = {}
+    for name in names:
+        tot, cnt = ctx.profile_read(name)
+        if cnt:
+            out[name] = {"avg_ms": tot / cnt, "launches": cnt}
+    ctx.profile_read("", reset=True)
+    ctx.profile(False)
+    return out
+
+
+def sources_digest():
+    h = hashlib.sha256()
+    for rel in GATHER_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the S = A R gather kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != sources_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(A, d, alpha, seed, budget_s=12.0):
@@ -75,13 +138,64 @@ def cpu_baseline(A, d, alpha, seed, budget_s=12.0):
     return t_tot / reps, cores, reps
 
 
+def rel_err(x, ref):
+    import torch
+    return float(torch.linalg.norm((x.double() - ref.double())) / torch.linalg.norm(ref.double()))
+
+
+def stored_leg(api, ctx, A, kind, d, seed, alpha, prec, steps, warmup, bytes_step):
+    import torch
+    try:
+        sk = api.Sketch(ctx, A, kind, d, seed, alpha=alpha, prec=prec, transpose=True)
+    except api.SketchError as e:
+        return {"unavailable": str(e)}, None
+    ms = time_steps(lambda i: sk.rerun(seed + i), steps, warmup)
+    names = KERNELS[prec if kind == "gaussian" and prec != "native" else kind]
+    kern = kernel_times(ctx, lambda i: sk.rerun(seed + i), names, max(3, steps // 2))
+    sk.rerun(seed)
+    torch.cuda.synchronize()
+    r = {"ms_per_step": ms, "GBps": bytes_step / (ms * 1e-3) / 1e9, "kernels": kern}
+    return r, sk
+
+
+def matrix_free_leg(api, ctx, steps, warmup):
+    import numpy as np
+    import torch
+
+    import workloads
+    c = workloads.cfg5()
+    N, d = c["N"], c["d"]
+    X = torch.from_numpy(c["X"]).cuda()
+    W = api.to_device_colmajor(np.asarray(c["W"]))
+    sk = api.Sketch(ctx, None, "sjlt", d, c["seed"], alpha=c["alpha"], points=(X, c["h"], 0.0))
+    fwd_ms = time_steps(lambda i: sk.rerun(c["seed"] + i), steps, warmup)
+    bsteps = max(2, steps // 4)
+    bwd_ms = time_steps(lambda i: sk.adjoint(W), bsteps, 1)
+    kern = kernel_times(ctx, lambda i: (sk.rerun(c["seed"] + i), sk.adjoint(W)),
+                        ("mf_fwd", "mf_bwd", "sjlt_meta", "sjlt_reduce"), max(2, steps // 4))
+    sk.release()
+    pairs = float(N) * N
+    # VALU lane-operations per (i, k) pair, counted from the kernels' arithmetic
+    # (dim = 3, alpha = 4; the transcendental exp2 issues at a quarter rate):
+    #   forward : 3 sub + 3 fma + 1 mul + exp2 (4 slots) + 4 signed fma          = 15
+    #   backward: 3 sub + 3 fma + 1 mul + exp2 (4) + 8 fma (G_ij, G_ji) + 3 fma
+    #             (dX terms) + 2 mul + cvt + f64 add (dh term)                   = 28
+    out = {"workload": "N=%d points in [0,1]^3, h=%.1f, SJLT alpha=%d, d=%d" % (N, c["h"], c["alpha"], d),
+           "forward_ms": round(fwd_ms, 4), "backward_ms": round(bwd_ms, 4), "kernels": kern}
+    for key, ops, name in (("forward", 15, "mf_fwd"), ("backward", 28, "mf_bwd")):
+        if name in kern:
+            ms = kern[name]["avg_ms"]
+            out[key + "_pairs_per_s"] = pairs / (ms * 1e-3)
+            out[key + "_valu_frac"] = round(pairs * ops / (ms * 1e-3) / VALU_LANE_OPS_PEAK, 4)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(every box has one MI355X); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import workloads
@@ -90,74 +204,102 @@ def main():
     c = workloads.cfg2()
     A_host, n, d, alpha, seed = c["A"], c["n"], c["d"], c["alpha"], c["seed"]
     A = api.to_device_colmajor(A_host)
-    esz = 8
-    bytes_sketch = n * n * esz + n * d * esz             # read A once, write the new columns
-    bytes_step = 2 * bytes_sketch                         # S and S'
+
+    def step_bytes(esz):
+        # read A once and write the new columns, for S and for S'
+        return 2 * (n * n * esz + n * d * esz)
 
     ctx = api.Context(0)
     results = {}
-    kinds = [k for k in args.kinds.split(",") if k]
+    sketches = {}
+
+    # measured copy bandwidth on this GPU (read + write of A's bytes)
+    B = torch.empty_like(A)
+    copy_ms = time_steps(lambda i: B.copy_(A), 10, 2)
+    del B
+    copy_gbps = 2 * A.numel() * 8 / (copy_ms * 1e-3) / 1e9
+    results["copy_reference"] = {"bytes_per_launch": 2 * A.numel() * 8, "ms": round(copy_ms, 4),
+                                 "GBps": round(copy_gbps, 1)}
+
+    kinds = ["sjlt"] if args.only_main else ["sjlt", "srht", "gaussian"]
     for kind in kinds:
+        r, sk = stored_leg(api, ctx, A, kind, d, seed, alpha, "native", args.steps, args.warmup, step_bytes(8))
+        results[kind] = r
+        if sk is not None:
+            sketches[kind] = sk
+
+    if not args.only_main:
+        # library FP64 GEMM (rocBLAS through torch) on the same shapes, for the
+        # "faster of the two" FP64 Gaussian baseline; R drawn by torch (timing only)
+        Rt = torch.randn(n, d, dtype=torch.float64, device="cuda")
+        At_row = A.T  # row-major view of the column-major A
+
+        def dgemm(i):
+            torch.mm(A, Rt)
+            torch.mm(At_row, Rt)
+        lib_ms = time_steps(dgemm, max(3, args.steps // 2), 1)
+        del Rt
+        g64 = results.get("gaussian", {})
+        base_ms = min([x for x in (g64.get("ms_per_step"), lib_ms) if x])
+        for kind in ("sjlt", "srht"):
+            if "ms_per_step" in results.get(kind, {}):
+                results[kind]["speedup_vs_fp64_gaussian"] = round(base_ms / results[kind]["ms_per_step"], 3)
+        if "ms_per_step" in g64:
+            flops = 2 * 2 * n * n * d
+            g64["TFLOPs"] = round(flops / (g64["ms_per_step"] * 1e-3) / 1e12, 2)
+            g64["frac_fp64_peak"] = round(g64["TFLOPs"] / FP64_PEAK_TFLOPS, 4)
+        results["fp64_gemm_library_ms"] = round(lib_ms, 4)
+        results["fp64_gaussian_baseline_ms"] = round(base_ms, 4)
+
+        # the same matrix rounded to FP32
+        A32 = A.float()
+        ref = {}
         try:
-            sk = api.Sketch(ctx, A, kind, d, seed, alpha=alpha, transpose=True)
-        except api.SketchError as e:
-            results[kind] = {"unavailable": str(e)}
-            continue
-        ms = time_steps(lambda i: sk.rerun(seed + i), args.steps, args.warmup)
-        # per-kernel times from HIP events recorded on the launch stream
-        ctx.profile(True)
-        ctx.profile_read("", reset=True)
-        nprof = max(3, args.steps // 2)
-        for i in range(nprof):
-            sk.rerun(seed + 1000 + i)
-        torch.cuda.synchronize()
-        kern = {}
-        for name in KERNELS[kind]:
-            tot, cnt = ctx.profile_read(name)
-            if cnt:
-                kern[name] = {"avg_ms": tot / cnt, "launches": cnt}
-        ctx.profile_read("", reset=True)
-        ctx.profile(False)
-        results[kind] = {"ms_per_step": ms, "GBps": bytes_step / (ms * 1e-3) / 1e9, "kernels": kern}
-        sk.release()
+            sk = api.Sketch(ctx, A32, "gaussian", d, seed, prec="native", transpose=True)
+            torch.cuda.synchronize()
+            ref = {"S": sk.S.clone(), "St": sk.St.clone()}
+            sk.release()
+        except api.SketchError:
+            pass
+        fp32 = {}
+        for kind, prec in (("sjlt", "native"), ("srht", "native"), ("gaussian", "bf16x3"), ("gaussian", "bf16")):
+            key = kind if prec == "native" else prec
+            r, sk = stored_leg(api, ctx, A32, kind, d, seed, alpha, prec, args.steps, args.warmup, step_bytes(4))
+            if sk is not None:
+                if kind == "gaussian" and ref:
+                    r["rel_err_vs_fp64_arith"] = max(rel_err(sk.S, ref["S"]), rel_err(sk.St, ref["St"]))
+                    flops = (3 if prec == "bf16x3" else 1) * 2 * 2 * n * n * d
+                    r["mfma_TFLOPs"] = round(flops / (r["ms_per_step"] * 1e-3) / 1e12, 2)
+                    r["frac_bf16_peak"] = round(r["mfma_TFLOPs"] / BF16_PEAK_TFLOPS, 4)
+                r["speedup_vs_fp64_gaussian"] = round(base_ms / r["ms_per_step"], 3)
+                sk.release()
+            fp32[key] = r
+        del A32, ref
+        results["fp32_matrix"] = fp32
+        results["matrix_free"] = matrix_free_leg(api, ctx, args.steps, args.warmup)
 
-    # library FP64 GEMM (rocBLAS through torch) on the same shapes, for the
-    # "faster of the two" FP64 Gaussian baseline; R drawn by torch (timing only)
-    Rt = torch.randn(n, d, dtype=torch.float64, device="cuda")
-    At_row = A.T  # row-major view of the column-major A
-    def dgemm(i):
-        torch.mm(A, Rt)
-        torch.mm(At_row, Rt)
-    lib_ms = time_steps(dgemm, max(3, args.steps // 2), 1)
-    del Rt
-    g64 = results.get("gaussian", {})
-    base_ms = min([x for x in (g64.get("ms_per_step"), lib_ms) if x])
-    for kind in ("sjlt", "srht"):
-        if "ms_per_step" in results.get(kind, {}):
-            results[kind]["speedup_vs_fp64_gaussian"] = round(base_ms / results[kind]["ms_per_step"], 3)
-    if "ms_per_step" in g64:
-        flops = 2 * 2 * n * n * d
-        g64["TFLOPs"] = round(flops / (g64["ms_per_step"] * 1e-3) / 1e12, 2)
-        g64["frac_fp64_peak"] = round(g64["TFLOPs"] / FP64_PEAK_TFLOPS, 4)
-    results["fp64_gemm_library_ms"] = round(lib_ms, 4)
-    results["fp64_gaussian_baseline_ms"] = round(base_ms, 4)
-
-    main_kind = "sjlt"
-    r = results[main_kind]
+    # the timed step: SJLT, S and S' of the FP64 matrix
+    r = results["sjlt"]
     ms = r["ms_per_step"]
     value = r["GBps"]
     g = r["kernels"].get("sjlt_gather")
     roof = None
     if g:
+        bytes_sketch = n * n * 8 + n * d * 8
         ach = bytes_sketch / (g["avg_ms"] * 1e-3) / 1e9
-        roof = {"kernel": "sjlt_gather_kernel (S = A R)", "bound": "hbm", "achieved": round(ach, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": bytes_sketch, "avg_launch_ms": g["avg_ms"]}
+        traffic = recorded_traffic()
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "sjlt_gather_kernel (S = A R)", "bytes_per_launch": bytes_sketch,
+                "avg_launch_ms": g["avg_ms"], "frac_of_measured_copy": round(ach / copy_gbps, 4),
+                "source_digest": sources_digest()}
+    for sk in sketches.values():
+        sk.release()
 
     cpu = None
     if not args.no_cpu_baseline:
         t_cpu, cores, reps = cpu_baseline(A_host, d, alpha, seed)
-        cpu = {"value": round(bytes_step / t_cpu / 1e9, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
+        cpu = {"value": round(step_bytes(8) / t_cpu / 1e9, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
                "sample": "full workload (operator + S + S', n=16384, d=256) x %d reps, %.2f s each" % (reps, t_cpu)}
 
     out = {
@@ -176,6 +318,7 @@ def main():
         "config": {"workload": "cauchy16k: FP64 Cauchy A_ij = 1/(x_i - y_j), n=16384, column-major, "
                                "SJLT alpha=4, d=256, S and S' per step", "n": n, "d": d, "alpha": alpha},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        "pct_measured_copy": round(100 * value / copy_gbps, 2),
         "roofline": roof,
         "cpu_baseline": cpu,
         "kinds": results,
