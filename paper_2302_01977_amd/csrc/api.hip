@@ -164,7 +164,7 @@ static int add_block(Handle* h, int32_t w) {
     const int64_t nT = (h->n + h->kc - 1) / h->kc;
     if (!rc) rc = dev_alloc(&b.codes, (size_t)h->n * h->alpha);
     if (!rc) rc = dev_alloc(&b.ptr, (size_t)nT * (w + 1));
-    if (!rc) rc = dev_alloc(&b.ent, (size_t)h->n * h->alpha);
+    if (!rc) rc = dev_alloc(&b.ent, (size_t)nT * sjlt_kcap(h->kc, h->alpha, w));
   } else if (h->kind == SK_GAUSSIAN) {
     if (!rc) rc = dev_alloc(&b.gbf, (size_t)h->n * w);
   } else if (h->kind == SK_SRHT) {

@@ -55,3 +55,77 @@ __device__ __forceinline__ void gather_chunk(const int32_t* __restrict__ P, cons
 }
 
 }  // namespace sk
+
+namespace sk {
+
+// Bucket gather with the chunk's entries staged in LDS.  E holds EW words per
+// entry: word 0 is the LDS address of the entry's source row in the staged tile
+// (XOR the lane's part gives the lane's address) and the last one (FP32) or
+// two (FP64) words the sign as a +-1.0 of type T.  The wave's bucket bounds
+// arrive in a VGPR (lane jj holds the start of column jj, bndN the end of the
+// last column).
+//
+// Bucket lengths vary (about KC * alpha / w entries per column and chunk), and
+// a data-dependent loop per column leaves one dependent chain of LDS reads in
+// flight.  So the first ms (4 or 8) slots of every bucket are gathered by
+// straight-line code (slots past the bucket's end read the zero row at zaddr),
+// four independent reads at a time; the rest of a longer bucket (even length)
+// follows in pairs.
+template <typename T, int NJ, int RPL, typename VT>
+__device__ __forceinline__ void gather_chunk_lds(const uint32_t* E, int ebase, uint32_t bnd, uint32_t bndN,
+                                                 uint32_t lane_part, uint32_t zaddr, int ms,
+                                                 T (&acc)[NJ][RPL]) {
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(3))) const VT* lds_vt;
+  constexpr int EW = sizeof(T) == 8 ? 4 : 2;
+  auto entry = [&](int e, uint32_t& addr, T& sgn) {
+    if constexpr (EW == 4) {
+      const u4 a = *(const u4*)&E[e * 4];
+      addr = a[0] ^ lane_part;
+      sgn = __builtin_bit_cast(T, ((uint64_t)a[3] << 32) | a[2]);
+    } else {
+      const uint32_t* p = &E[e * 2];
+      addr = p[0] ^ lane_part;
+      sgn = __builtin_bit_cast(T, p[1]);
+    }
+  };
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) {
+    const int e0 = (int)__builtin_amdgcn_readlane(bnd, jj) - ebase;
+    const int e1 = (jj + 1 < NJ ? (int)__builtin_amdgcn_readlane(bnd, jj + 1)
+                                : (int)__builtin_amdgcn_readfirstlane(bndN)) - ebase;
+    // slots [e0 + m0, e0 + m0 + 4), masked past the bucket's end
+    auto four = [&](int m0) {
+      uint32_t ad[4];
+      T sg[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        entry(e0 + m0 + q, ad[q], sg[q]);
+        ad[q] = e0 + m0 + q < e1 ? ad[q] : zaddr;
+      }
+      VT x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = *(lds_vt)(uintptr_t)ad[q];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        T a = acc[jj][r];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a = fma(((const T*)&x[q])[r], sg[q], a);
+        acc[jj][r] = a;
+      }
+    };
+    four(0);
+    if (ms > 4) four(4);  // buckets of about eight entries: eight straight-line slots
+    for (int e = e0 + ms; e < e1; e += 2) {
+      uint32_t a0, a1;
+      T s0, s1;
+      entry(e, a0, s0);
+      entry(e + 1, a1, s1);
+      const VT x0 = *(lds_vt)(uintptr_t)a0, x1 = *(lds_vt)(uintptr_t)a1;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[jj][r] = fma(((const T*)&x1)[r], s1, fma(((const T*)&x0)[r], s0, acc[jj][r]));
+    }
+  }
+}
+
+}  // namespace sk

@@ -102,7 +102,15 @@ struct SjltPass {
   int32_t grp_col[MAX_PASS_GROUPS];
   const int32_t* ptr[MAX_PASS_BLOCKS];
   const int32_t* ent[MAX_PASS_BLOCKS];
+  int32_t nblk;     // blocks in the pass
+  int32_t kcap;     // entry slots of one block per chunk (sjlt_kcap)
+  int32_t ms;       // straight-line bucket slots in the LDS-staged gather (4 or 8)
 };
+
+// Entry slots reserved per chunk of one block: the chunk's KC * alpha entries,
+// plus one null entry for each bucket of odd length (buckets are padded to even
+// length), rounded up to 256 so that chunk regions start on 1 KB boundaries.
+inline int sjlt_kcap(int kc, int alpha, int w) { return (kc * alpha + w + 255) / 256 * 256; }
 
 // ---- launchers (each returns SK_OK or an error code after checking the launch)
 int launch_sjlt_meta(Handle* h, Block& b, hipStream_t st);

@@ -29,9 +29,12 @@ __global__ void __launch_bounds__(256) sjlt_hash_kernel(uint32_t* __restrict__ c
 }
 
 // Bucket table, chunk-major: ptr[t * (w + 1) + j] = first entry of column j in
-// chunk t.  The count kernel stores counts there with slot w of every chunk set
-// to 0, so that an exclusive scan of the whole table gives the bucket starts and,
-// in slot w, the end of the chunk.
+// chunk t; slot w holds the end of the chunk's entries.  Chunk t owns the entry
+// slots [t * kcap, (t + 1) * kcap).  Every bucket is padded to an even length
+// with a null entry (source KC, sign +), which the gather kernels map to a
+// staged source slot of zeros; unused slots of the region hold null entries too.
+// The count kernel stores the padded counts, chunk_scan_kernel turns them into
+// starts.
 __global__ void __launch_bounds__(256) sjlt_count_kernel(const uint32_t* __restrict__ codes,
                                                          int32_t* __restrict__ ptr, int64_t n, int alpha,
                                                          int w, int kc) {
@@ -43,29 +46,19 @@ __global__ void __launch_bounds__(256) sjlt_count_kernel(const uint32_t* __restr
   const int nk = (int)min((int64_t)kc, n - k0);
   for (int e = threadIdx.x; e < nk * alpha; e += blockDim.x) atomicAdd(&cnt[codes[k0 * alpha + e] >> 1], 1);
   __syncthreads();
-  for (int j = threadIdx.x; j <= w; j += blockDim.x) ptr[(int64_t)t * (w + 1) + j] = j < w ? cnt[j] : 0;
+  for (int j = threadIdx.x; j <= w; j += blockDim.x)
+    ptr[(int64_t)t * (w + 1) + j] = j < w ? cnt[j] + (cnt[j] & 1) : 0;
 }
 
-// In-place exclusive scan of M ints with one workgroup of 1024 threads.
-__global__ void __launch_bounds__(1024) exclusive_scan_kernel(int32_t* __restrict__ a, int64_t M) {
-  __shared__ int32_t part[1024];
-  const int tid = threadIdx.x;
-  const int64_t seg = (M + 1023) / 1024;
-  const int64_t s0 = min(M, tid * seg), s1 = min(M, s0 + seg);
-  int32_t sum = 0;
-  for (int64_t i = s0; i < s1; ++i) sum += a[i];
-  part[tid] = sum;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int32_t v = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  int32_t run = part[tid] - sum;
-  for (int64_t i = s0; i < s1; ++i) {
-    const int32_t c = a[i];
-    a[i] = run;
+// Exclusive scan of each chunk's w + 1 padded counts, offset by the chunk's
+// region start (one workgroup per chunk; thread 0 walks the row in order).
+__global__ void __launch_bounds__(64) chunk_scan_kernel(int32_t* __restrict__ ptr, int w, int kcap) {
+  if (threadIdx.x != 0) return;
+  int32_t* row = ptr + (int64_t)blockIdx.x * (w + 1);
+  int32_t run = (int32_t)blockIdx.x * kcap;
+  for (int j = 0; j <= w; ++j) {
+    const int32_t c = row[j];
+    row[j] = run;
     run += c;
   }
 }
@@ -76,13 +69,14 @@ __global__ void __launch_bounds__(1024) exclusive_scan_kernel(int32_t* __restric
 __global__ void __launch_bounds__(KC_MAX) sjlt_scatter_kernel(const uint32_t* __restrict__ codes,
                                                               const int32_t* __restrict__ ptr,
                                                               int32_t* __restrict__ ent, int64_t n, int alpha,
-                                                              int w, int kc) {
+                                                              int w, int kc, int kcap) {
   __shared__ uint32_t sc[KC_MAX * 32];
   const int t = blockIdx.x;
   const int kk = threadIdx.x;
   const int64_t k0 = (int64_t)t * kc;
   const int nk = (int)min((int64_t)kc, n - k0);
   for (int e = threadIdx.x; e < nk * alpha; e += blockDim.x) sc[e] = codes[k0 * alpha + e];
+  for (int e = threadIdx.x; e < kcap; e += blockDim.x) ent[(int64_t)t * kcap + e] = kc << 1;  // null entries
   __syncthreads();
   if (kk >= nk) return;
   for (int c = 0; c < alpha; ++c) {
@@ -105,9 +99,10 @@ int launch_sjlt_meta(Handle* h, Block& b, hipStream_t st) {
   SK_HIP(hipGetLastError());
   sjlt_count_kernel<<<nT, 256, 0, st>>>(b.codes, b.ptr, n, h->alpha, b.w, kc);
   SK_HIP(hipGetLastError());
-  exclusive_scan_kernel<<<1, 1024, 0, st>>>(b.ptr, (int64_t)nT * (b.w + 1));
+  const int kcap = sjlt_kcap(kc, h->alpha, b.w);
+  chunk_scan_kernel<<<nT, 64, 0, st>>>(b.ptr, b.w, kcap);
   SK_HIP(hipGetLastError());
-  sjlt_scatter_kernel<<<nT, kc, 0, st>>>(b.codes, b.ptr, b.ent, n, h->alpha, b.w, kc);
+  sjlt_scatter_kernel<<<nT, kc, 0, st>>>(b.codes, b.ptr, b.ent, n, h->alpha, b.w, kc, kcap);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }

@@ -30,7 +30,7 @@ template <int NW, int NJ, int KCK, int DIM>
 __global__ void __launch_bounds__(NW * 64)
     mf_sjlt_kernel(const float* __restrict__ X, int64_t N, float c2, float shift, SjltPass pass,
                    float* __restrict__ out, int64_t ldo, float scale, int split, float* __restrict__ part) {
-  __shared__ __attribute__((aligned(16))) float tile[KCK * 64];
+  __shared__ __attribute__((aligned(16))) float tile[(KCK + 1) * 64];  // slot KCK: zeros for null entries
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -51,6 +51,7 @@ __global__ void __launch_bounds__(NW * 64)
   float xi[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) xi[d] = i < N ? X[i * DIM + d] : 0.f;
+  if (tid < 64) tile[KCK * 64 + tid] = 0.f;
 
   float acc[NJ][1];
 #pragma unroll

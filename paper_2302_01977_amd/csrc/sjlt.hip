@@ -62,7 +62,7 @@ struct VecT<double, 2> {
   typedef f64x2 type;
 };
 
-template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK>
+template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK, bool LDSE>
 __global__ void __launch_bounds__(NW * 64)
     sjlt_gather_kernel(const T* __restrict__ A, int64_t lda, int64_t L, int64_t K, SjltPass pass,
                        T* __restrict__ out, int64_t ldo, T scale, int split, T* __restrict__ part) {
@@ -77,7 +77,18 @@ __global__ void __launch_bounds__(NW * 64)
   static_assert(RPL <= VECN, "a lane reads at most one 16-byte chunk");
   typedef typename VecT<T, RPL>::type VT;
 
-  __shared__ __attribute__((aligned(16))) T tile[KCK * TL];
+  // Dynamic LDS: the staged tile, whose extra source slot KCK holds zeros (the
+  // source of null entries), then (LDSE) the chunk's bucket entries, EW words
+  // each: the entry's LDS address in the tile and its sign as +-1.0.
+  constexpr int NSLOT = KCK + 1;
+  constexpr int EW = SZ == 8 ? 4 : 2;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  T* tile = (T*)smem;
+  uint32_t* ents = (uint32_t*)(smem + NSLOT * TL * SZ);
+  // LDS address of the tile.  The kernel has no static LDS, so the dynamic
+  // block starts at 0 and the tile base is a multiple of the row stride TL * SZ:
+  // base + row offset + swizzle key combine with the lane part by XOR.
+  const uint32_t tile_lds = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char*)smem;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -93,6 +104,25 @@ __global__ void __launch_bounds__(NW * 64)
   const int64_t prow = pass.wtot[blk] + 1;
   const int32_t* __restrict__ ptr = pass.ptr[blk] + jb;
   const int32_t* __restrict__ ent = pass.ent[blk];
+
+  // LDSE staging of entries: thread tid moves entries [4 tid, 4 tid + 4) and
+  // [4 (tid + NTHR), ...) of the concatenated chunk regions of the pass's blocks
+  // (kcap is a multiple of 256, so a wave's entries lie in one block)
+  int q0[2], eloc[2];
+  bool e_on[2];
+  const uint32_t* __restrict__ eptr[2];
+  u32x4 ebuf[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    q0[h] = (tid + h * NTHR) * 4;
+    const int eb = LDSE ? __builtin_amdgcn_readfirstlane(q0[h] / pass.kcap) : 0;
+    eloc[h] = q0[h] - eb * (LDSE ? pass.kcap : 0);
+    e_on[h] = LDSE && eb < pass.nblk;
+    eptr[h] = e_on[h] ? (const uint32_t*)pass.ent[eb] + eloc[h] : nullptr;
+    ebuf[h] = u32x4{0u, 0u, 0u, 0u};
+  }
+  uint32_t bnd = 0, bndN = 0, bnd_nx = 0, bndN_nx = 0;
+  for (int e = tid; e < TL; e += NTHR) tile[KCK * TL + e] = T(0);
 
   // ---------------------------------------------------------------- staging
   u32x4 buf[NV];
@@ -115,7 +145,20 @@ __global__ void __launch_bounds__(NW * 64)
       gc = l0 + ((int64_t)my_cb + (int64_t)(it / VECN) * CBSTEP) * VECN + (it % VECN);
     }
   };
+  auto load_meta = [&](int t) {
+    if constexpr (LDSE) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)  // whole regions: null entries past the end
+        if (e_on[h]) ebuf[h] = *(const u32x4*)(eptr[h] + (int64_t)t * pass.kcap);
+      if (active) {
+        const int32_t* pb = ptr + (int64_t)t * prow;
+        bnd_nx = lane < NJ ? (uint32_t)pb[lane] : 0u;
+        bndN_nx = (uint32_t)pb[NJ];
+      }
+    }
+  };
   auto load_chunk = [&](int t) {
+    load_meta(t);
     const int64_t k0 = (int64_t)t * KCK;
     const bool full = l0 + TL <= L && k0 + KCK <= K;  // uniform
     if (full) {
@@ -144,6 +187,30 @@ __global__ void __launch_bounds__(NW * 64)
     }
   };
   auto store_chunk = [&]() {
+    if constexpr (LDSE) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (!e_on[h]) continue;
+        uint32_t ad[4], sg[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t src = ebuf[h][q] >> 1;
+          ad[q] = (tile_lds + src * (uint32_t)(TL * SZ)) | (TRANS ? ((src / VECN) & 15u) * 16u : 0u);
+          // the sign as +-1.0 (high word of the double for FP64)
+          sg[q] = ((ebuf[h][q] & 1u) << 31) | (SZ == 8 ? 0x3ff00000u : 0x3f800000u);
+        }
+        const int qb = q0[h];
+        if constexpr (EW == 4) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) *(u32x4*)&ents[(qb + q) * 4] = u32x4{ad[q], 0u, 0u, sg[q]};
+        } else {
+          *(u32x4*)&ents[qb * 2] = u32x4{ad[0], sg[0], ad[1], sg[1]};
+          *(u32x4*)&ents[qb * 2 + 4] = u32x4{ad[2], sg[2], ad[3], sg[3]};
+        }
+      }
+      bnd = bnd_nx;
+      bndN = bndN_nx;
+    }
     if (!TRANS) {
 #pragma unroll
       for (int it = 0; it < NV; ++it) *(u32x4*)(&tile[(my_col + it * CSTEP) * TL + my_row]) = buf[it];
@@ -177,6 +244,10 @@ __global__ void __launch_bounds__(NW * 64)
   const uint32_t lane_q16 = (uint32_t)(lane_elem / VECN) * 16u;  // S': 16-byte chunk before the swizzle
   const uint32_t lane_in = (uint32_t)(lane_elem % VECN) * SZ;     // S': offset inside the chunk
   const uint32_t lane_off = (uint32_t)lane_elem * SZ;             // S
+  // LDSE: an entry's address is its staged word XOR this lane's part (the
+  // source's row offset and the S' swizzle key occupy disjoint bits)
+  const uint32_t lane_part = TRANS ? (lane_q16 | lane_in) : lane_off;
+  const uint32_t zaddr = (tile_lds + (uint32_t)(KCK * TL * SZ)) ^ lane_part;  // this lane's zero of slot KCK
   const char* tbase = (const char*)tile;
 
   auto LD = [&](int v) -> VT {
@@ -197,7 +268,12 @@ __global__ void __launch_bounds__(NW * 64)
     store_chunk();
     __syncthreads();
     if (t + 1 < t1) load_chunk(t + 1);  // in flight during the gather below
-    if (active) gather_chunk<T, NJ, RPL, VT>(ptr + (int64_t)t * prow, ent, LD, acc);
+    if (active) {
+      if constexpr (LDSE)
+        gather_chunk_lds<T, NJ, RPL, VT>(ents, (t - blk) * pass.kcap, bnd, bndN, lane_part, zaddr, pass.ms, acc);
+      else
+        gather_chunk<T, NJ, RPL, VT>(ptr + (int64_t)t * prow, ent, LD, acc);
+    }
   }
 
   if (!active) return;
@@ -237,17 +313,30 @@ void split_reduce_f32(const float* part, int split, int64_t L, int64_t W, float*
 }
 
 // ------------------------------------------------------------------ dispatch
+// dynamic LDS of one workgroup: the tile with its zero slot, then the entries
+static size_t gather_lds_bytes(int esz, int kc, int tl, bool ldse, int nblk, int kcap) {
+  const size_t ew = esz == 8 ? 16 : 8;
+  return (size_t)(kc + 1) * tl * esz + (ldse ? ((size_t)nblk * kcap + 4) * ew : 0);
+}
+
 struct GatherCfg {
   int nw, nj, rpl, kc;
+  bool ldse;  // bucket entries staged in LDS (else read through the scalar cache)
 };
 
-template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK>
+template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK, bool LDSE>
 static int run_gather(Ctx* c, const T* A, int64_t lda, int64_t L, int64_t K, const SjltPass& pass, T* out,
                       int64_t ldo, T scale, int split, T* part, int gz, hipStream_t st) {
   dim3 grid((unsigned)((L + 64 * RPL - 1) / (64 * RPL)), (unsigned)split, (unsigned)gz);
+  const size_t shmem = gather_lds_bytes((int)sizeof(T), KCK, 64 * RPL, LDSE, pass.nblk, pass.kcap);
+  auto kern = sjlt_gather_kernel<T, TRANS, NW, NJ, RPL, KCK, LDSE>;
+  static bool attr_set = false;  // once per instantiation (the limit is the same on every device)
+  if (!attr_set) {
+    SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr_set = true;
+  }
   ProfScope ps(c, TRANS ? "sjlt_gather_t" : "sjlt_gather", st);
-  sjlt_gather_kernel<T, TRANS, NW, NJ, RPL, KCK>
-      <<<grid, NW * 64, 0, st>>>(A, lda, L, K, pass, out, ldo, scale, split, part);
+  kern<<<grid, NW * 64, shmem, st>>>(A, lda, L, K, pass, out, ldo, scale, split, part);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }
@@ -266,7 +355,9 @@ static int try_cfg(const GatherCfg& cfg, Ctx* c, const T* A, int64_t lda, int64_
                    T* out, int64_t ldo, T scale, int split, T* part, int gz, hipStream_t st) {
   if (cfg.nw != NW || cfg.nj != NJ || cfg.rpl != RPL || cfg.kc != KCK) return 1;
   if constexpr (GatherValid<T, TRANS, NW, NJ, RPL, KCK>::value) {
-    return run_gather<T, TRANS, NW, NJ, RPL, KCK>(c, A, lda, L, K, pass, out, ldo, scale, split, part, gz, st);
+    if (cfg.ldse)
+      return run_gather<T, TRANS, NW, NJ, RPL, KCK, true>(c, A, lda, L, K, pass, out, ldo, scale, split, part, gz, st);
+    return run_gather<T, TRANS, NW, NJ, RPL, KCK, false>(c, A, lda, L, K, pass, out, ldo, scale, split, part, gz, st);
   } else {
     return 1;
   }
@@ -400,12 +491,24 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
     }
   }
 
+  pass.nblk = nblk;
+  pass.kcap = 0;
+  // straight-line slots per bucket: about the mean bucket length KC * alpha / w
+  pass.ms = (int64_t)h->kc * h->alpha >= 7LL * W / nblk ? 8 : 4;
+  for (int b = b0; b < b1; ++b) pass.kcap = std::max(pass.kcap, sjlt_kcap(h->kc, h->alpha, h->blocks[b].w));
+  // entries staged in LDS when every block of the pass has the same chunk region
+  // size, the regions fit four entries per thread and the LDS holds them
+  bool same = true;
+  for (int b = b0; b < b1; ++b) same = same && sjlt_kcap(h->kc, h->alpha, h->blocks[b].w) == pass.kcap;
+  const size_t esz = h->dtype == SK_F64 ? 8 : 4;
+  const int TL = 64 * cfg.rpl;
+  cfg.ldse = same && (int64_t)nblk * pass.kcap <= (int64_t)cfg.nw * 64 * 8 &&
+             gather_lds_bytes((int)esz, cfg.kc, TL, true, nblk, pass.kcap) <= 160 * 1024;
+
   const int64_t L = trans ? in->n : in->m;  // lanes
   const int64_t K = trans ? in->m : in->n;  // sources (= rows of R)
-  const int TL = 64 * cfg.rpl;
   const int64_t tiles = ((L + TL - 1) / TL) * gz;
-  const size_t esz = h->dtype == SK_F64 ? 8 : 4;
-  const size_t tile_bytes = (size_t)cfg.kc * TL * esz;
+  const size_t tile_bytes = gather_lds_bytes((int)esz, cfg.kc, TL, cfg.ldse, nblk, pass.kcap);
   const int64_t per_cu = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)tile_bytes);
   const int64_t target = per_cu * (int64_t)h->ctx->num_cu;
   int split = 1;
