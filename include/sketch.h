@@ -185,6 +185,51 @@ int sketch_profile_enable(sk_ctx *ctx, int32_t on);
  * reset != 0 clears every record.  Synchronises on the recorded events. */
 int sketch_profile_read(sk_ctx *ctx, const char *name, double *ms, int64_t *count, int32_t reset);
 
+/* ---- batched sketches ----------------------------------------------------
+ * Many independent stored matrices, each compressed adaptively with its own
+ * SJLT operator grown in blocks of dd columns (Algorithm 1's extension step
+ * S <- [S, A Rbar], run for a whole batch).  Round r draws block r of every
+ * operator whose target width d[i] exceeds r * dd and computes
+ *   S_i(:, r dd : (r+1) dd) = A_i R_i,r   (and S'_i = A_i^T R_i,r when St != NULL)
+ * in one persistent launch over all (matrix, row tile) work items, after four
+ * batched operator-generation launches.  Operators are identical to the ones
+ * sketch_apply/sketch_extend draw for (seed[i], blocks of width dd, alpha). */
+typedef struct sk_batch sk_batch;
+
+#define SK_BATCH_GRAPH 1    /* capture each round in a HIP graph on first run, replay it afterwards */
+#define SK_BATCH_AUTOTUNE 2 /* time the candidate tile shapes on this batch and keep the fastest
+                               (cached in the context per batch signature); synchronises */
+
+/* sketch_batch_create: plan a batch of `count` SK_DENSE matrices ins[i] (one
+ * dtype; m, n <= 2^31 - 1; S' needs m == n) with final widths d[i] (positive
+ * multiples of dd), block width dd in {64, 128, 256}, alpha | dd, operator seeds
+ * seeds[i] and outputs outs[i] (S: m_i x d[i], ldS >= m_i; St: n_i x d[i] or
+ * NULL).  The input and output buffers must stay valid for the batch's life:
+ * their addresses are recorded (and baked into the graphs).  Allocates the
+ * operator metadata of every (matrix, block); uploads on `stream` and
+ * synchronises it.  *b receives the batch; release with sketch_batch_destroy.
+ * Errors: SK_EINVAL, SK_EUNSUPPORTED (other block widths), SK_ENOMEM, SK_EHIP. */
+int sketch_batch_create(sk_ctx *ctx, const sk_input *ins, int32_t count, const int32_t *d, int32_t dd,
+                        int32_t alpha, const uint64_t *seeds, const sk_output *outs, int32_t flags, sk_batch **b,
+                        void *stream);
+
+/* sketch_batch_run: run rounds [r0, r1) in order on `stream` (asynchronous).
+ * With SK_BATCH_GRAPH the first run of a round captures it (on a private
+ * stream) and every run launches the instantiated graph. */
+int sketch_batch_run(sk_batch *b, int32_t r0, int32_t r1, void *stream);
+
+/* sketch_batch_reseed: new operator seeds for the following runs (the graphs
+ * read them from device memory).  Synchronises `stream`. */
+int sketch_batch_reseed(sk_batch *b, const uint64_t *seeds, void *stream);
+
+/* sketch_batch_info: number of rounds and the tile shape in use:
+ * shape[0..3] = (sources per chunk, waves per workgroup, columns per wave, rows
+ * per lane). */
+int sketch_batch_info(const sk_batch *b, int32_t *nrounds, int32_t *shape);
+
+/* sketch_batch_destroy: free the batch (synchronises the device). */
+int sketch_batch_destroy(sk_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,6 +14,7 @@ SK_GAUSSIAN, SK_SJLT, SK_SRHT = 0, 1, 2
 SK_F64, SK_F32 = 0, 1
 SK_PREC_NATIVE, SK_PREC_BF16, SK_PREC_BF16X3 = 0, 1, 2
 SK_DENSE, SK_POINTS = 0, 1
+SK_BATCH_GRAPH, SK_BATCH_AUTOTUNE = 1, 2
 
 c_i32, c_i64, c_u64, c_f32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float, ctypes.c_void_p
 
@@ -47,6 +48,12 @@ _SIGS = {
     "sketch_get_sjlt": (c_i32, [c_vp, c_i32, c_vp]),
     "sketch_get_srht": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32]),
     "sketch_get_gaussian": (c_i32, [c_vp, c_i32, c_vp]),
+    "sketch_batch_create": (c_i32, [c_vp, P(SkInput), c_i32, c_vp, c_i32, c_i32, c_vp, P(SkOutput), c_i32,
+                                    P(c_vp), c_vp]),
+    "sketch_batch_run": (c_i32, [c_vp, c_i32, c_i32, c_vp]),
+    "sketch_batch_reseed": (c_i32, [c_vp, c_vp, c_vp]),
+    "sketch_batch_info": (c_i32, [c_vp, P(c_i32), c_vp]),
+    "sketch_batch_destroy": (c_i32, [c_vp]),
     "sketch_profile_enable": (c_i32, [c_vp, c_i32]),
     "sketch_profile_read": (c_i32, [c_vp, ctypes.c_char_p, P(ctypes.c_double), P(c_i64), c_i32]),
 }

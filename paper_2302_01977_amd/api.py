@@ -244,6 +244,71 @@ class Sketch:
             pass
 
 
+class Batch:
+    """Batched SJLT sketches of many stored matrices (sketch_batch_*).
+
+    ``Batch(ctx, mats, d, dd, seeds)`` plans S_i = A_i R_i for every device
+    matrix ``mats[i]`` (column-major, one dtype) with target width ``d[i]``
+    built in blocks of ``dd``; ``run()`` computes all rounds into ``self.S[i]``
+    (and ``self.St[i]`` with ``transpose=True``).
+    """
+
+    def __init__(self, ctx, mats, d, dd, seeds, alpha=4, transpose=False, graph=True, autotune=False,
+                 stream=None):
+        self._lib = abi.load()
+        self.ctx = ctx
+        count = len(mats)
+        if not (len(d) == count and len(seeds) == count and count >= 1):
+            raise ValueError("mats, d and seeds must have the same positive length")
+        self._keep = list(mats)
+        ins = (abi.SkInput * count)()
+        outs = (abi.SkOutput * count)()
+        self.S, self.St = [], []
+        for i, A in enumerate(mats):
+            ins[i] = dense_input(A, False)
+            S = colmajor(A.shape[0], d[i], A.dtype, A.device)
+            St = colmajor(A.shape[1], d[i], A.dtype, A.device) if transpose else None
+            self.S.append(S)
+            self.St.append(St)
+            outs[i] = _output(S, St)
+        self._ins, self._outs = ins, outs
+        self.count = count
+        darr = (ctypes.c_int32 * count)(*[int(x) for x in d])
+        sarr = (ctypes.c_uint64 * count)(*[int(x) for x in seeds])
+        flags = (abi.SK_BATCH_GRAPH if graph else 0) | (abi.SK_BATCH_AUTOTUNE if autotune else 0)
+        self.h = ctypes.c_void_p()
+        _check(self._lib.sketch_batch_create(ctx.ptr, ins, count, darr, dd, alpha, sarr, outs, flags,
+                                             ctypes.byref(self.h), _stream(stream)))
+        ctx._live.add(self)
+
+    def run(self, r0=0, r1=None, stream=None):
+        if r1 is None:
+            r1 = self.info()[0]
+        _check(self._lib.sketch_batch_run(self.h, r0, r1, _stream(stream)))
+
+    def reseed(self, seeds, stream=None):
+        sarr = (ctypes.c_uint64 * self.count)(*[int(x) for x in seeds])
+        _check(self._lib.sketch_batch_reseed(self.h, sarr, _stream(stream)))
+
+    def info(self):
+        """(number of rounds, (chunk, waves, columns per wave, rows per lane))"""
+        nr = ctypes.c_int32()
+        shape = (ctypes.c_int32 * 4)()
+        _check(self._lib.sketch_batch_info(self.h, ctypes.byref(nr), shape))
+        return nr.value, tuple(shape)
+
+    def release(self):
+        if self.h:
+            _check(self._lib.sketch_batch_destroy(self.h))
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
 def _as_colmajor(T):
     if T.dim() == 2 and (T.stride(0) == 1 or T.shape[0] == 1):
         return T

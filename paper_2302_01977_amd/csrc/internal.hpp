@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -64,6 +65,8 @@ struct Ctx {
   bool prof = false;
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
+  // autotuner results: shape key -> tuned parameters
+  std::map<std::string, std::vector<int>> tune;
 };
 
 // Brackets one kernel launch with HIP events on its stream when profiling is on.
@@ -112,7 +115,19 @@ struct SjltPass {
 // length), rounded up to 256 so that chunk regions start on 1 KB boundaries.
 inline int sjlt_kcap(int kc, int alpha, int w) { return (kc * alpha + w + 255) / 256 * 256; }
 
+// One SJLT operator block to generate in a batched launch.
+struct MetaItem {
+  uint32_t* codes;  // n * alpha
+  int32_t* ptr;     // nT * (w + 1)
+  int32_t* ent;     // nT * kcap
+  int64_t n;
+  int32_t w, alpha, kc, kcap, block;
+  uint32_t k0, k1;  // Philox key of the operator's seed
+};
+
 // ---- launchers (each returns SK_OK or an error code after checking the launch)
+int launch_sjlt_meta_batch(const MetaItem* items, const int2* rows, int nrows, const int2* chunks, int nchunks,
+                           int kc, hipStream_t st);
 int launch_sjlt_meta(Handle* h, Block& b, hipStream_t st);
 int launch_srht_meta(Handle* h, int64_t j0, int64_t j1, bool draw_D, hipStream_t st);
 int launch_gauss_meta(Handle* h, Block& b, hipStream_t st);

@@ -10,10 +10,8 @@
 
 namespace sk {
 
-__global__ void __launch_bounds__(256) sjlt_hash_kernel(uint32_t* __restrict__ codes, int64_t n, int alpha,
-                                                        uint32_t wc, uint32_t block, Key key) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+__device__ __forceinline__ void hash_row(uint32_t* __restrict__ codes, int64_t k, int alpha, uint32_t wc,
+                                         uint32_t block, Key key) {
   const uint32_t sbits = philox(2u, block, (uint32_t)k, 0u, key.k0, key.k1).v[0];
   for (int c4 = 0; c4 < alpha; c4 += 4) {
     const U4 o = philox(1u, block, (uint32_t)k, (uint32_t)(c4 >> 2), key.k0, key.k1);
@@ -28,18 +26,20 @@ __global__ void __launch_bounds__(256) sjlt_hash_kernel(uint32_t* __restrict__ c
   }
 }
 
+__global__ void __launch_bounds__(256) sjlt_hash_kernel(uint32_t* __restrict__ codes, int64_t n, int alpha,
+                                                        uint32_t wc, uint32_t block, Key key) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) hash_row(codes, k, alpha, wc, block, key);
+}
+
 // Bucket table, chunk-major: ptr[t * (w + 1) + j] = first entry of column j in
 // chunk t; slot w holds the end of the chunk's entries.  Chunk t owns the entry
 // slots [t * kcap, (t + 1) * kcap).  Every bucket is padded to an even length
 // with a null entry (source KC, sign +), which the gather kernels map to a
 // staged source slot of zeros; unused slots of the region hold null entries too.
-// The count kernel stores the padded counts, chunk_scan_kernel turns them into
-// starts.
-__global__ void __launch_bounds__(256) sjlt_count_kernel(const uint32_t* __restrict__ codes,
-                                                         int32_t* __restrict__ ptr, int64_t n, int alpha,
-                                                         int w, int kc) {
-  __shared__ int cnt[1024];
-  const int t = blockIdx.x;
+// count_chunk stores the padded counts, scan_chunk turns them into starts.
+__device__ __forceinline__ void count_chunk(const uint32_t* __restrict__ codes, int32_t* __restrict__ ptr,
+                                            int64_t n, int alpha, int w, int kc, int t, int* cnt) {
   for (int j = threadIdx.x; j < w; j += blockDim.x) cnt[j] = 0;
   __syncthreads();
   const int64_t k0 = (int64_t)t * kc;
@@ -50,12 +50,19 @@ __global__ void __launch_bounds__(256) sjlt_count_kernel(const uint32_t* __restr
     ptr[(int64_t)t * (w + 1) + j] = j < w ? cnt[j] + (cnt[j] & 1) : 0;
 }
 
-// Exclusive scan of each chunk's w + 1 padded counts, offset by the chunk's
-// region start (one workgroup per chunk; thread 0 walks the row in order).
-__global__ void __launch_bounds__(64) chunk_scan_kernel(int32_t* __restrict__ ptr, int w, int kcap) {
+__global__ void __launch_bounds__(256) sjlt_count_kernel(const uint32_t* __restrict__ codes,
+                                                         int32_t* __restrict__ ptr, int64_t n, int alpha,
+                                                         int w, int kc) {
+  __shared__ int cnt[1024];
+  count_chunk(codes, ptr, n, alpha, w, kc, blockIdx.x, cnt);
+}
+
+// Exclusive scan of chunk t's w + 1 padded counts, offset by the chunk's region
+// start (thread 0 walks the row in order).
+__device__ __forceinline__ void scan_chunk(int32_t* __restrict__ ptr, int w, int kcap, int t) {
   if (threadIdx.x != 0) return;
-  int32_t* row = ptr + (int64_t)blockIdx.x * (w + 1);
-  int32_t run = (int32_t)blockIdx.x * kcap;
+  int32_t* row = ptr + (int64_t)t * (w + 1);
+  int32_t run = (int32_t)t * kcap;
   for (int j = 0; j <= w; ++j) {
     const int32_t c = row[j];
     row[j] = run;
@@ -63,15 +70,16 @@ __global__ void __launch_bounds__(64) chunk_scan_kernel(int32_t* __restrict__ pt
   }
 }
 
-// One workgroup per chunk, one thread per source; a source's rank inside its
-// bucket counts the earlier sources of the chunk in the same bucket, so every
-// bucket lists its sources in ascending order.
-__global__ void __launch_bounds__(KC_MAX) sjlt_scatter_kernel(const uint32_t* __restrict__ codes,
-                                                              const int32_t* __restrict__ ptr,
-                                                              int32_t* __restrict__ ent, int64_t n, int alpha,
-                                                              int w, int kc, int kcap) {
-  __shared__ uint32_t sc[KC_MAX * 32];
-  const int t = blockIdx.x;
+__global__ void __launch_bounds__(64) chunk_scan_kernel(int32_t* __restrict__ ptr, int w, int kcap) {
+  scan_chunk(ptr, w, kcap, blockIdx.x);
+}
+
+// One thread per source of chunk t; a source's rank inside its bucket counts the
+// earlier sources of the chunk in the same bucket, so every bucket lists its
+// sources in ascending order.
+__device__ __forceinline__ void scatter_chunk(const uint32_t* __restrict__ codes, const int32_t* __restrict__ ptr,
+                                              int32_t* __restrict__ ent, int64_t n, int alpha, int w, int kc,
+                                              int kcap, int t, uint32_t* sc) {
   const int kk = threadIdx.x;
   const int64_t k0 = (int64_t)t * kc;
   const int nk = (int)min((int64_t)kc, n - k0);
@@ -86,6 +94,61 @@ __global__ void __launch_bounds__(KC_MAX) sjlt_scatter_kernel(const uint32_t* __
     for (int q = 0; q < kk; ++q) rank += (sc[q * alpha + c] >> 1) == col;
     ent[ptr[(int64_t)t * (w + 1) + col] + rank] = (kk << 1) | (int)(code & 1u);
   }
+}
+
+__global__ void __launch_bounds__(KC_MAX) sjlt_scatter_kernel(const uint32_t* __restrict__ codes,
+                                                              const int32_t* __restrict__ ptr,
+                                                              int32_t* __restrict__ ent, int64_t n, int alpha,
+                                                              int w, int kc, int kcap) {
+  __shared__ uint32_t sc[KC_MAX * 32];
+  scatter_chunk(codes, ptr, ent, n, alpha, w, kc, kcap, blockIdx.x, sc);
+}
+
+// ---- batched: one launch per step over the blocks of many operators; list[i]
+// = (item, row block of 256 sources) for hashing, (item, chunk) otherwise
+__global__ void __launch_bounds__(256) sjlt_hash_batch(const MetaItem* __restrict__ items,
+                                                       const int2* __restrict__ list) {
+  const int2 l = list[blockIdx.x];
+  const MetaItem& m = items[l.x];
+  const int64_t k = (int64_t)l.y + threadIdx.x;
+  if (k < m.n) hash_row(m.codes, k, m.alpha, (uint32_t)(m.w / m.alpha), (uint32_t)m.block, Key{m.k0, m.k1});
+}
+
+__global__ void __launch_bounds__(256) sjlt_count_batch(const MetaItem* __restrict__ items,
+                                                        const int2* __restrict__ list) {
+  __shared__ int cnt[1024];
+  const int2 l = list[blockIdx.x];
+  const MetaItem& m = items[l.x];
+  count_chunk(m.codes, m.ptr, m.n, m.alpha, m.w, m.kc, l.y, cnt);
+}
+
+__global__ void __launch_bounds__(64) chunk_scan_batch(const MetaItem* __restrict__ items,
+                                                       const int2* __restrict__ list) {
+  const int2 l = list[blockIdx.x];
+  const MetaItem& m = items[l.x];
+  scan_chunk(m.ptr, m.w, m.kcap, l.y);
+}
+
+__global__ void __launch_bounds__(KC_MAX) sjlt_scatter_batch(const MetaItem* __restrict__ items,
+                                                             const int2* __restrict__ list) {
+  __shared__ uint32_t sc[KC_MAX * 32];
+  const int2 l = list[blockIdx.x];
+  const MetaItem& m = items[l.x];
+  scatter_chunk(m.codes, m.ptr, m.ent, m.n, m.alpha, m.w, m.kc, m.kcap, l.y, sc);
+}
+
+int launch_sjlt_meta_batch(const MetaItem* items, const int2* rows, int nrows, const int2* chunks, int nchunks,
+                           int kc, hipStream_t st) {
+  if (nrows == 0 || nchunks == 0) return SK_OK;
+  sjlt_hash_batch<<<nrows, 256, 0, st>>>(items, rows);
+  SK_HIP(hipGetLastError());
+  sjlt_count_batch<<<nchunks, 256, 0, st>>>(items, chunks);
+  SK_HIP(hipGetLastError());
+  chunk_scan_batch<<<nchunks, 64, 0, st>>>(items, chunks);
+  SK_HIP(hipGetLastError());
+  sjlt_scatter_batch<<<nchunks, kc, 0, st>>>(items, chunks);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
 }
 
 int launch_sjlt_meta(Handle* h, Block& b, hipStream_t st) {
