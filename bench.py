@@ -14,6 +14,8 @@ Reported beside it, on the same GPU and in the same run:
     each with its relative error against the FP64-arithmetic Gaussian path;
   * the matrix-free kernel sketch and its backward (N = 32768 points in 3-D,
     d = 256);
+  * the batched sketch of 96 kernel matrices of uneven size, one persistent
+    graph launch per round, against per-matrix launches;
   * a measured copy bandwidth (torch copy of A), the reference for the HBM
     counters;
   * the FP64 CPU oracle timed on the host cores (a reported baseline).
@@ -41,7 +43,8 @@ BF16_PEAK_TFLOPS = 2500.0
 # VALU issue without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 # the dominant kernel's sources: the traffic figures below are valid only for them
-GATHER_SOURCES = ("paper_2302_01977_amd/csrc/sjlt.hip", "paper_2302_01977_amd/csrc/gather.hpp")
+GATHER_SOURCES = ("paper_2302_01977_amd/csrc/sjlt.hip", "paper_2302_01977_amd/csrc/sjlt_tile.hpp",
+                  "paper_2302_01977_amd/csrc/gather.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sjlt_gather_cauchy16k_traffic.txt")
 
 
@@ -190,6 +193,50 @@ def matrix_free_leg(api, ctx, steps, warmup):
     return out
 
 
+def batch_leg(api, ctx, steps, warmup):
+    """96 FP32 Gaussian-kernel matrices of uneven size (n_i log-uniform in
+    [512, 8192]), SJLT alpha = 4, each grown in blocks of 64 to its own d_i in
+    {64, ..., 256}: every round as one persistent launch replayed from a HIP
+    graph, against one launch pair (operator block + sketch) per matrix and
+    round.  The matrices are formed on the device from the seeded points."""
+    import torch
+
+    import workloads
+    specs = workloads.cfg4_specs()
+    seeds = [workloads.OP_SEED[4] + i for i in range(len(specs))]
+    mats = []
+    for sp in specs:
+        X = torch.from_numpy(workloads.uniform_points(sp["n"], 2, sp["point_seed"])).cuda()
+        D2 = torch.cdist(X, X) ** 2
+        K = torch.exp(-D2 / (2.0 * sp["h"] ** 2)).float().contiguous()
+        mats.append(K.t())  # symmetric: the transposed view is the column-major matrix
+        del X, D2
+    d = [sp["d"] for sp in specs]
+    nbytes = sum(sp["n"] * sp["n"] * 4 * (sp["d"] // 64) + sp["n"] * sp["d"] * 4 for sp in specs)
+    b = api.Batch(ctx, mats, d, 64, seeds, graph=True, autotune=True)
+    nr, shape = b.info()
+    ms_b = time_steps(lambda i: b.run(), steps, warmup)
+    kern = kernel_times(ctx, lambda i: b.run(), ("sjlt_batch",), max(2, steps // 4))
+    b.release()
+    # baseline: one single-block handle per (matrix, round), rerun one by one
+    hs = []
+    for r in range(nr):
+        for i, sp in enumerate(specs):
+            if d[i] > 64 * r:
+                hs.append((api.Sketch(ctx, mats[i], "sjlt", 64, seeds[i] + 7919 * r), seeds[i] + 7919 * r))
+    ms_p = time_steps(lambda i: [h.rerun(s0) for h, s0 in hs], steps, warmup)
+    for h, _ in hs:
+        h.release()
+    del mats
+    torch.cuda.empty_cache()
+    return {"workload": "96 FP32 Gaussian-kernel matrices, n_i in [512, 8192], d_i in {64..256}, blocks of 64, "
+                        "SJLT alpha=4", "rounds": nr, "tile_shape": shape, "launches_per_matrix_path": 2 * len(hs),
+            "batched_graph_ms": round(ms_b, 4), "per_matrix_ms": round(ms_p, 4),
+            "batched_GBps": round(nbytes / (ms_b * 1e-3) / 1e9, 1),
+            "per_matrix_GBps": round(nbytes / (ms_p * 1e-3) / 1e9, 1),
+            "speedup_vs_per_matrix": round(ms_p / ms_b, 3), "kernels": kern}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -277,6 +324,7 @@ def main():
         del A32, ref
         results["fp32_matrix"] = fp32
         results["matrix_free"] = matrix_free_leg(api, ctx, args.steps, args.warmup)
+        results["batched"] = batch_leg(api, ctx, max(3, args.steps // 2), 2)
 
     # the timed step: SJLT, S and S' of the FP64 matrix
     r = results["sjlt"]
