@@ -5,7 +5,7 @@
  *   S  = A R     (section 1: post-multiplication of A by a tall random n x d R)
  *   S' = A^T R   (section 1: needed for the row space when A is nonsymmetric;
  *                 A is real here, so A^* = A^T)
- * where R = [R_0 | R_1 | ...] is a Gaussian, SJLT or SRHT operator (section 2.3),
+ * where R = [R_0 | R_1 | ...] is a Gaussian, SJLT or SRHT operator (section 2.4),
  * grown block by block as Algorithm 1 appends JL-Operator(dd, n) columns.
  *
  * Conventions for every entry point
@@ -40,7 +40,7 @@ extern "C" {
 #define SK_EHIP (-4)         /* a HIP runtime call failed; the message carries hipGetErrorString */
 #define SK_ESTATE (-5)       /* released, foreign or corrupted handle/context */
 
-/* operator kinds (section 2.3) */
+/* operator kinds (section 2.4) */
 #define SK_GAUSSIAN 0 /* i.i.d. N(0, 1/w_b) entries (values on the bfloat16 grid) */
 #define SK_SJLT 1     /* block construction: alpha chunks of w_b/alpha columns, one +-1/sqrt(alpha) per chunk and row */
 #define SK_SRHT 2     /* R = D H P / sqrt(w_b)-scaled; D Rademacher, H Sylvester-Hadamard (natural order), P uniform samples */

@@ -11,7 +11,7 @@ Contents (each function cites the passage of the paper it follows):
              std::minstd_rand so that every operator entry is a pure function of
              (seed, counter)).
   operators  explicit FP64 blocks of the Gaussian, SJLT (block construction) and
-             SRHT operators of section 2.3, the SRHT element formula of
+             SRHT operators of section 2.4, the SRHT element formula of
              section 7.2, the SJLT B+/B- split of section 6.1.
   sketch     S = A R, S' = A^T R, sampled columns, the adjoint dS R^T, the
              matrix-free Gaussian-kernel sketch and its closed-form gradient.

@@ -4,7 +4,7 @@ Test infrastructure only (see ``oracle/__init__.py``).
 
 The operator R = [R_0 | R_1 | ...] is a concatenation of blocks; block b has width
 w_b and starts at global column c_b.  Each block is its own JL operator normalised
-by its own width (reading of section 2.3 "Gaussian Sketching Operator" together
+by its own width (reading of section 2.4.1 "Gaussian Sketching Operator" together
 with the extension step of Algorithm 1, which appends a fresh JL-Operator(dd, n)).
 
 Random draws come from Philox4x32-10 (``oracle.philox``) under key = seed, with
@@ -32,7 +32,7 @@ SJLT_MAX_ALPHA = 32
 def sjlt_hash(n, w, alpha, block, seed):
     """Nonzero positions and signs of one SJLT block (block construction).
 
-    Section 2.3 "Sparse Johnson-Lindenstrauss Transform": every row holds alpha
+    Section 2.4.3 "Sparse Johnson-Lindenstrauss Transform": every row holds alpha
     nonzeros +-1/sqrt(alpha).  Block construction, read as: the row of width w is
     cut into alpha chunks of w/alpha consecutive columns and each chunk holds
     exactly one nonzero at a uniform position (the printed text says d/alpha
@@ -99,7 +99,7 @@ def is_pow2(n):
 
 
 def srht_diag(n, seed):
-    """Rademacher diagonal D (section 2.3 SRHT): int64 array of +-1, length n."""
+    """Rademacher diagonal D (section 2.4.2 SRHT): int64 array of +-1, length n."""
     key = key_from_seed(seed)
     w0 = philox4x32_10(3, 0, np.arange(n, dtype=np.uint64), 0, key)[0]
     return 1 - 2 * (w0 & np.uint64(1)).astype(np.int64)
@@ -109,7 +109,7 @@ def srht_samples(nu, j0, j1, seed):
     """Sampled Hadamard columns mu_j for global columns j0 <= j < j1.
 
     Each column of P is drawn independently and uniformly from the nu canonical
-    vectors (section 2.3 SRHT and section 7.2), i.e. with replacement.
+    vectors (section 2.4.2 SRHT and section 7.2), i.e. with replacement.
     """
     key = key_from_seed(seed)
     j = np.arange(j0, j1, dtype=np.uint64)
@@ -121,7 +121,7 @@ def srht_samples(nu, j0, j1, seed):
 def hadamard(nu):
     """Unnormalised Sylvester-Hadamard matrix H_nu (+-1 entries, natural order).
 
-    Built by the recursion H_1 = [1], H_2m = [[H_m, H_m], [H_m, -H_m]] of section 2.3.
+    Built by the recursion H_1 = [1], H_2m = [[H_m, H_m], [H_m, -H_m]] of section 2.4.2.
     """
     H = np.ones((1, 1), dtype=np.float64)
     while H.shape[0] < nu:
@@ -170,7 +170,7 @@ def gaussian_raw(n, col0, w, seed):
 
     Box-Muller on two Philox words: U = (u + 0.5) 2^-32, z = sqrt(-2 ln U1) cos(2 pi U2),
     evaluated in FP64 and rounded to bfloat16 so that the value is exactly
-    representable in bf16, fp32 and fp64 (section 2.3 "Gaussian Sketching Operator"
+    representable in bf16, fp32 and fp64 (section 2.4.1 "Gaussian Sketching Operator"
     asks for N(0, 1/d) entries; the bf16 grid is this build's reading, see the
     design notes).
     """

@@ -1,4 +1,4 @@
-// Gaussian sketch S = A R_b on the matrix cores (section 2.3: R_b has i.i.d.
+// Gaussian sketch S = A R_b on the matrix cores (section 2.4.1: R_b has i.i.d.
 // N(0, 1/w_b) entries; the product is a dense contraction, O(m n w) flops).
 // The draws g are stored on the bfloat16 grid, column-major; the 1/sqrt(w_b)
 // scale is applied to the result.

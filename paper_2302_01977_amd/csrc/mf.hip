@@ -1,7 +1,7 @@
 // Matrix-free Gaussian-kernel sketch S = K(X, h) R with an SJLT R, and its
 // hand-written backward.  K_ij = exp(-|x_i - x_j|^2 / (2 h^2)) (+ shift on the
 // diagonal) is never stored: every kernel recomputes the tiles it needs.
-// (The paper's construction is only partially matrix-free, section 2.2; here the
+// (The paper's construction is only partially matrix-free, section 2.3; here the
 // sketch itself is.)
 //
 // Forward: the stored-A SJLT gather with the LDS tile produced in registers:

@@ -46,7 +46,7 @@ def test_key_and_mulhi():
 # --------------------------------------------------------------------- SJLT
 @pytest.mark.parametrize("n,w,alpha", [(100, 64, 4), (257, 64, 8), (64, 256, 4), (33, 8, 1)])
 def test_sjlt_structure(n, w, alpha):
-    """Section 2.3, block construction (alpha chunks of w/alpha columns, one
+    """Section 2.4.3, block construction (alpha chunks of w/alpha columns, one
     nonzero +-1/sqrt(alpha) each): exactly alpha nonzeros per row, one per chunk,
     unit row norms, ||R||_F^2 = n."""
     R = ops.sjlt_block(n, w, alpha, block=3, seed=77)
@@ -70,7 +70,7 @@ def test_sjlt_blocks_differ_and_are_deterministic():
 
 
 def test_sjlt_positions_uniform_and_signs_balanced():
-    """Offsets are uniform over each chunk and signs are fair coins (section 2.3)."""
+    """Offsets are uniform over each chunk and signs are fair coins (section 2.4.3)."""
     n, w, alpha = 40000, 64, 4
     cols, signs = ops.sjlt_hash(n, w, alpha, 0, 5)
     wc = w // alpha
@@ -99,7 +99,7 @@ def test_sjlt_worked_example_split():
 # --------------------------------------------------------------------- SRHT
 @pytest.mark.parametrize("nu", [1, 2, 4, 64, 1024])
 def test_hadamard_orthogonal(nu):
-    """Section 2.3: the Sylvester recursion gives H H^T = nu I (unnormalised)."""
+    """Section 2.4.2: the Sylvester recursion gives H H^T = nu I (unnormalised)."""
     H = ops.hadamard(nu)
     assert (H @ H.T == nu * np.eye(nu)).all()
 
@@ -114,7 +114,7 @@ def test_hadamard_element_formula_matches_recursion():
 
 
 def test_srht_block_equals_DHP():
-    """Section 2.3 R = D H P with P's columns sqrt(nu/w) e_mu; the element formula
+    """Section 2.4.2 R = D H P with P's columns sqrt(nu/w) e_mu; the element formula
     of section 7.2 must give the same matrix as the explicit product."""
     n, w, col0, seed = 128, 24, 40, 9
     D = ops.srht_diag(n, seed)
