@@ -89,6 +89,8 @@ static void free_block(Block& b) {
   if (b.codes) (void)hipFree(b.codes);
   if (b.ptr) (void)hipFree(b.ptr);
   if (b.ent) (void)hipFree(b.ent);
+  if (b.ptr_t) (void)hipFree(b.ptr_t);
+  if (b.ent_t) (void)hipFree(b.ent_t);
   if (b.gbf) (void)hipFree(b.gbf);
   if (b.gf64) (void)hipFree(b.gf64);
   b = Block();
@@ -165,6 +167,11 @@ static int add_block(Handle* h, int32_t w) {
     if (!rc) rc = dev_alloc(&b.codes, (size_t)h->n * h->alpha);
     if (!rc) rc = dev_alloc(&b.ptr, (size_t)nT * (w + 1));
     if (!rc) rc = dev_alloc(&b.ent, (size_t)nT * sjlt_kcap(h->kc, h->alpha, w));
+    if (h->kct) {
+      const int64_t nTt = (h->n + h->kct - 1) / h->kct;
+      if (!rc) rc = dev_alloc(&b.ptr_t, (size_t)nTt * (w + 1));
+      if (!rc) rc = dev_alloc(&b.ent_t, (size_t)nTt * sjlt_kcap(h->kct, h->alpha, w));
+    }
   } else if (h->kind == SK_GAUSSIAN) {
     if (!rc) rc = dev_alloc(&b.gbf, (size_t)h->n * w);
   } else if (h->kind == SK_SRHT) {
@@ -339,7 +346,14 @@ int sketch_apply(sk_ctx* ctx, const sk_input* in, const sk_op_desc* op, int32_t 
   h->n = op_rows(in);
   h->seed = seed;
   hipStream_t st = (hipStream_t)stream;
-  if (h->kind == SK_SJLT) h->kc = sjlt_chunk_for(d, h->alpha);
+  if (h->kind == SK_SJLT) {
+    if (in->input == SK_DENSE) {
+      sjlt_pick_chunks(h->dtype, d, h->alpha, out && out->St, &h->kc, &h->kct);
+    } else {
+      h->kc = sjlt_chunk_for(d, h->alpha, 4);
+      h->kct = 0;
+    }
+  }
   int rc = validate_width(h, d);
   if (!rc && h->kind == SK_SRHT) rc = dev_alloc(&h->srht_D, (size_t)h->n);
   if (!rc && h->kind == SK_SRHT) {

@@ -147,7 +147,7 @@ static std::vector<BatchCfg> batch_candidates(int dtype, int dd, int alpha) {
 
 static BatchCfg batch_default(int dtype, int dd, int alpha) {
   std::vector<BatchCfg> c = batch_candidates(dtype, dd, alpha);
-  const int kc = sjlt_chunk_for(dd, alpha);
+  const int kc = sjlt_chunk_for(dd, alpha, 4);
   const int rpl = dtype == SK_F32 ? (kc == 64 ? 4 : kc == 128 ? 2 : 1) : (kc == 64 ? 2 : 1);
   for (const BatchCfg& b : c)
     if (b.kc == kc && b.rpl == rpl) return b;
@@ -266,7 +266,7 @@ static int build_rounds(Batch* b, const BatchCfg& c, int max_rounds, hipStream_t
       R.meta_matrix.push_back(i);
       for (int64_t k0 = 0; k0 < n; k0 += 256) rows.push_back(make_int2(mi, (int)k0));
       for (int t = 0; t < nT; ++t) chunks.push_back(make_int2(mi, t));
-      const int ms = (int64_t)c.kc * b->alpha >= 7LL * b->dd ? 8 : 4;
+      const int ms = (int64_t)c.kc * b->alpha >= 7LL * b->dd ? 8 : 4;  // straight-line slots (4 or 8)
       const sk_output& o = b->outs[i];
       const size_t esz = b->dtype == SK_F64 ? 8 : 4;
       for (int tr = 0; tr < 2; ++tr) {

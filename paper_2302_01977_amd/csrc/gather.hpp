@@ -4,6 +4,7 @@
 // (entry & 1); the source's RPL values of this lane are read from LDS through
 // LD(entry) and added with that sign.  Entries are wave-uniform (scalar loads).
 #pragma once
+#include <type_traits>
 #include "internal.hpp"
 
 namespace sk {
@@ -117,6 +118,63 @@ __device__ __forceinline__ void gather_chunk_lds(const uint32_t* E, int ebase, u
     four(0);
     if (ms > 4) four(4);  // buckets of about eight entries: eight straight-line slots
     for (int e = e0 + ms; e < e1; e += 2) {
+      uint32_t a0, a1;
+      T s0, s1;
+      entry(e, a0, s0);
+      entry(e + 1, a1, s1);
+      const VT x0 = *(lds_vt)(uintptr_t)a0, x1 = *(lds_vt)(uintptr_t)a1;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[jj][r] = fma(((const T*)&x1)[r], s1, fma(((const T*)&x0)[r], s0, acc[jj][r]));
+    }
+  }
+}
+
+// The same gather with the straight-line slot count MS (2, 4 or 8) fixed at
+// compile time, for kernels instantiated per bucket-length class.
+template <typename T, int NJ, int RPL, typename VT, int MS>
+__device__ __forceinline__ void gather_chunk_lds_ms(const uint32_t* E, int ebase, uint32_t bnd, uint32_t bndN,
+                                                    uint32_t lane_part, uint32_t zaddr, T (&acc)[NJ][RPL]) {
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(3))) const VT* lds_vt;
+  constexpr int EW = sizeof(T) == 8 ? 4 : 2;
+  constexpr int NQ = MS < 4 ? MS : 4;
+  auto entry = [&](int e, uint32_t& addr, T& sgn) {
+    if constexpr (EW == 4) {
+      const u4 a = *(const u4*)&E[e * 4];
+      addr = a[0] ^ lane_part;
+      sgn = __builtin_bit_cast(T, ((uint64_t)a[3] << 32) | a[2]);
+    } else {
+      const uint32_t* p = &E[e * 2];
+      addr = p[0] ^ lane_part;
+      sgn = __builtin_bit_cast(T, p[1]);
+    }
+  };
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) {
+    const int e0 = (int)__builtin_amdgcn_readlane(bnd, jj) - ebase;
+    const int e1 = (jj + 1 < NJ ? (int)__builtin_amdgcn_readlane(bnd, jj + 1)
+                                : (int)__builtin_amdgcn_readfirstlane(bndN)) - ebase;
+#pragma unroll
+    for (int m0 = 0; m0 < MS; m0 += NQ) {
+      uint32_t ad[NQ];
+      T sg[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        entry(e0 + m0 + q, ad[q], sg[q]);
+        ad[q] = e0 + m0 + q < e1 ? ad[q] : zaddr;
+      }
+      VT x[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) x[q] = *(lds_vt)(uintptr_t)ad[q];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        T a = acc[jj][r];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) a = fma(((const T*)&x[q])[r], sg[q], a);
+        acc[jj][r] = a;
+      }
+    }
+    for (int e = e0 + MS; e < e1; e += 2) {
       uint32_t a0, a1;
       T s0, s1;
       entry(e, a0, s0);

@@ -42,7 +42,9 @@ struct Block {
   // SJLT metadata
   uint32_t* codes = nullptr;  // n * alpha: (col << 1) | neg
   int32_t* ptr = nullptr;     // nT * (w + 1): bucket starts, chunk-major (ptr[t * (w + 1) + j])
-  int32_t* ent = nullptr;     // n * alpha (+8): (local source << 1) | neg, sorted by (chunk, col, source)
+  int32_t* ent = nullptr;     // nT * kcap: (local source << 1) | neg, sorted by (chunk, col, source)
+  int32_t* ptr_t = nullptr;   // the same tables for S' when it uses another chunk size (Handle::kct)
+  int32_t* ent_t = nullptr;
   // Gaussian draws of the block: bf16 bits, n x w column-major (k contiguous)
   uint16_t* gbf = nullptr;
   // Gaussian draws as FP64, w x n (row j of R^T contiguous over k) for the FP64 kernel
@@ -85,6 +87,7 @@ struct Handle {
   int32_t kind = 0, alpha = 1, prec = 0, dtype = 0, input = 0;
   int64_t n = 0;  // rows of R
   int32_t kc = 64;  // SJLT: sources per chunk of the bucket tables
+  int32_t kct = 0;  // SJLT: chunk of the S' tables when it differs from kc (0: S' uses the S tables)
   uint64_t seed = 0;
   int32_t d = 0;
   std::vector<Block> blocks;
@@ -147,8 +150,15 @@ int launch_sjlt_adjoint(Handle* h, const sk_input* in, int b0, int b1, const voi
 void split_reduce_f32(const float* part, int split, int64_t L, int64_t W, float* out, int64_t ldo, float scale,
                       hipStream_t st);
 
+int launch_sjlt_dma(Ctx* c, int dtype, int nw, int nj, int rpl, int kc, const void* A, int64_t lda, int64_t L,
+                    int64_t K, const SjltPass& pass, void* out, int64_t ldo, double scale, int split, void* part,
+                    int gz, hipStream_t st);
+size_t dma_lds_bytes(int esz, int kc, int tl, int nblk, int kcap);
+
 int ensure_work(Ctx* c, size_t bytes);
-int sjlt_chunk_for(int w, int alpha);
+int sjlt_chunk_for(int w, int alpha, int lam);
+// chunk sizes of a new dense SJLT operator of width d: for S, and for S'
+void sjlt_pick_chunks(int dtype, int d, int alpha, bool want_t, int* kc, int* kct);
 
 }  // namespace sk
 

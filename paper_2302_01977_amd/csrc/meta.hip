@@ -167,6 +167,17 @@ int launch_sjlt_meta(Handle* h, Block& b, hipStream_t st) {
   SK_HIP(hipGetLastError());
   sjlt_scatter_kernel<<<nT, kc, 0, st>>>(b.codes, b.ptr, b.ent, n, h->alpha, b.w, kc, kcap);
   SK_HIP(hipGetLastError());
+  if (b.ptr_t) {  // S' tables with their own chunk size
+    const int kt = h->kct;
+    const int nTt = (int)((n + kt - 1) / kt);
+    const int kcapt = sjlt_kcap(kt, h->alpha, b.w);
+    sjlt_count_kernel<<<nTt, 256, 0, st>>>(b.codes, b.ptr_t, n, h->alpha, b.w, kt);
+    SK_HIP(hipGetLastError());
+    chunk_scan_kernel<<<nTt, 64, 0, st>>>(b.ptr_t, b.w, kcapt);
+    SK_HIP(hipGetLastError());
+    sjlt_scatter_kernel<<<nTt, kt, 0, st>>>(b.codes, b.ptr_t, b.ent_t, n, h->alpha, b.w, kt, kcapt);
+    SK_HIP(hipGetLastError());
+  }
   return SK_OK;
 }
 

@@ -134,10 +134,46 @@ static int gcd_int(int a, int b) {
   return a;
 }
 
-int sjlt_chunk_for(int w, int alpha) {
-  // about four entries per bucket and chunk: KC * alpha / w >= 4
+// Shape of the direct-to-LDS S kernel for a pass: every column group in one
+// workgroup (nw * nj == W), the double-buffered tile and entries in LDS, the
+// entries within the staging capacity; nw = 0 when none fits.
+struct DmaShape {
+  int nw, nj, rpl;
+};
+static DmaShape choose_dma(int dtype, int kc, int W, int g, int nblk, int kcap) {
+  static const int f64[][4] = {{128, 16, 16, 1}, {128, 8, 32, 1}, {128, 8, 16, 1}, {128, 4, 16, 1},
+                               {64, 16, 16, 1},  {64, 8, 16, 2}};
+  static const int f32[][4] = {{256, 16, 16, 1}, {256, 8, 32, 1}, {128, 16, 16, 2},
+                               {128, 8, 16, 2},  {128, 16, 16, 1}};
+  const int esz = dtype == SK_F64 ? 8 : 4;
+  const int(*tab)[4] = dtype == SK_F64 ? f64 : f32;
+  const int ntab = dtype == SK_F64 ? (int)(sizeof(f64) / sizeof(f64[0])) : (int)(sizeof(f32) / sizeof(f32[0]));
+  for (int i = 0; i < ntab; ++i) {
+    const int* r = tab[i];
+    if (r[0] != kc || r[1] * r[2] != W || g % r[2] != 0) continue;
+    if ((int64_t)nblk * kcap > (int64_t)r[1] * 64 * 8) continue;
+    if (dma_lds_bytes(esz, kc, 64 * r[3], nblk, kcap) > 160 * 1024) continue;
+    return DmaShape{r[1], r[2], r[3]};
+  }
+  return DmaShape{0, 0, 0};
+}
+
+// Chunk sizes of a dense operator of width d.  S: about two entries per bucket
+// when the direct-to-LDS kernel has a shape for it (it double-buffers the tile,
+// so shorter chunks keep it in LDS), else about four.  S': about four in FP64,
+// two in FP32 (register-staged kernel, measured on MI355X).  kct = 0 when S'
+// shares the S tables.
+void sjlt_pick_chunks(int dtype, int d, int alpha, bool want_t, int* kc, int* kct) {
+  const int k2 = sjlt_chunk_for(d, alpha, 2);
+  *kc = choose_dma(dtype, k2, d, d, 1, sjlt_kcap(k2, alpha, d)).nw ? k2 : sjlt_chunk_for(d, alpha, 4);
+  const int kt = sjlt_chunk_for(d, alpha, dtype == SK_F64 ? 4 : 2);
+  *kct = want_t && kt != *kc ? kt : 0;
+}
+
+int sjlt_chunk_for(int w, int alpha, int lam) {
+  // smallest chunk with about lam entries per bucket (KC * alpha / w >= lam)
   int kc = 64;
-  while (kc < 256 && kc * alpha < 4 * w) kc *= 2;
+  while (kc < 256 && kc * alpha < lam * w) kc *= 2;
   return kc;
 }
 
@@ -176,7 +212,10 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
     g = gcd_int(g, h->blocks[b].w);
   }
   SK_REQUIRE(g % 16 == 0, SK_EINVAL, "SJLT block widths must be multiples of 16");
-  GatherCfg cfg = choose_cfg(h->dtype, h->kc, W, g);
+  // S' may use bucket tables of its own chunk size
+  const bool own_t = trans && h->kct && h->blocks[b0].ptr_t;
+  const int kc = own_t ? h->kct : h->kc;
+  GatherCfg cfg = choose_cfg(h->dtype, kc, W, g);
   if (cfg.nw == 8) {
     const bool ok = h->dtype == SK_F64 ? (trans ? cfg_valid<double, true>(8, cfg.rpl, cfg.kc)
                                                : cfg_valid<double, false>(8, cfg.rpl, cfg.kc))
@@ -190,13 +229,13 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
 
   SjltPass pass;
   memset(&pass, 0, sizeof(pass));
-  pass.nT = (int)((h->n + h->kc - 1) / h->kc);
+  pass.nT = (int)((h->n + kc - 1) / kc);
   pass.ngroups = ngroups;
   int gi = 0;
   for (int b = b0; b < b1; ++b) {
     const Block& B = h->blocks[b];
-    pass.ptr[b - b0] = B.ptr;
-    pass.ent[b - b0] = B.ent;
+    pass.ptr[b - b0] = own_t ? B.ptr_t : B.ptr;
+    pass.ent[b - b0] = own_t ? B.ent_t : B.ent;
     pass.wtot[b - b0] = B.w;
     for (int c = 0; c < B.w; c += cfg.nj) {
       pass.grp_blk[gi] = b - b0;
@@ -208,12 +247,15 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
   pass.nblk = nblk;
   pass.kcap = 0;
   // straight-line slots per bucket: about the mean bucket length KC * alpha / w
-  pass.ms = (int64_t)h->kc * h->alpha >= 7LL * W / nblk ? 8 : 4;
-  for (int b = b0; b < b1; ++b) pass.kcap = std::max(pass.kcap, sjlt_kcap(h->kc, h->alpha, h->blocks[b].w));
+  {
+    const int64_t lam2 = 2LL * kc * h->alpha * nblk / W;  // twice the mean bucket length per chunk
+    pass.ms = lam2 >= 14 ? 8 : lam2 >= 6 ? 4 : 2;
+  }
+  for (int b = b0; b < b1; ++b) pass.kcap = std::max(pass.kcap, sjlt_kcap(kc, h->alpha, h->blocks[b].w));
   // entries staged in LDS when every block of the pass has the same chunk region
   // size, the regions fit four entries per thread and the LDS holds them
   bool same = true;
-  for (int b = b0; b < b1; ++b) same = same && sjlt_kcap(h->kc, h->alpha, h->blocks[b].w) == pass.kcap;
+  for (int b = b0; b < b1; ++b) same = same && sjlt_kcap(kc, h->alpha, h->blocks[b].w) == pass.kcap;
   const size_t esz = h->dtype == SK_F64 ? 8 : 4;
   const int TL = 64 * cfg.rpl;
   cfg.ldse = same && (int64_t)nblk * pass.kcap <= (int64_t)cfg.nw * 64 * 8 &&
@@ -225,6 +267,8 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
   const size_t tile_bytes = gather_lds_bytes((int)esz, cfg.kc, TL, cfg.ldse, nblk, pass.kcap);
   const int64_t per_cu = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)tile_bytes);
   const int64_t target = per_cu * (int64_t)h->ctx->num_cu;
+  const int ms_raw = pass.ms;
+  pass.ms = std::max(pass.ms, 4);  // the register-staged gather takes 4 or 8 straight-line slots
   int split = 1;
   if (tiles < target) split = (int)std::min<int64_t>((target + tiles - 1) / tiles, std::max(1, pass.nT / 4));
   void* part = nullptr;
@@ -236,6 +280,53 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
   const double scale = 1.0 / sqrt((double)h->alpha);
   Ctx* c = h->ctx;
   int rc;
+  // S with whole-workgroup column coverage: the direct-to-LDS kernel when a
+  // shape fits (it splits the source range by the same rule)
+  if (!trans) {
+    DmaShape ds = choose_dma(h->dtype, kc, W, g, nblk, pass.kcap);
+    if (ds.nw) {
+      const size_t dbytes = dma_lds_bytes((int)esz, kc, 64 * ds.rpl, nblk, pass.kcap);
+      const int64_t dtiles = (L + 64 * ds.rpl - 1) / (64 * ds.rpl);
+      const int64_t dtarget = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)dbytes) * c->num_cu;
+      int dsplit = 1;
+      if (dtiles < dtarget)
+        dsplit = (int)std::min<int64_t>((dtarget + dtiles - 1) / dtiles, std::max(1, pass.nT / 4));
+      SjltPass dp = pass;  // the register-staged pass below keeps its own column groups
+      dp.ms = ms_raw;
+      dp.ngroups = W / ds.nj;
+      int di = 0;
+      for (int b = b0; b < b1; ++b)
+        for (int cc = 0; cc < h->blocks[b].w; cc += ds.nj) {
+          dp.grp_blk[di] = b - b0;
+          dp.grp_col[di] = cc;
+          ++di;
+        }
+      void* dpart = nullptr;
+      if (dsplit > 1) {
+        if ((rc = ensure_work(c, (size_t)dsplit * (size_t)L * (size_t)W * esz))) return rc;
+        dpart = c->work;
+      }
+      rc = launch_sjlt_dma(c, h->dtype, ds.nw, ds.nj, ds.rpl, kc, in->A, in->lda, L, K, dp, out, ldo, scale,
+                           dsplit, dpart, 1, st);
+      if (rc != 1) {
+        if (rc) return rc;
+        if (dsplit > 1) {
+          const int64_t tot = L * (int64_t)W;
+          const unsigned nb = (unsigned)((tot + 255) / 256);
+          ProfScope ps(h->ctx, "sjlt_reduce", st);
+          if (h->dtype == SK_F64)
+            split_reduce_kernel<double><<<nb, 256, 0, st>>>((const double*)dpart, dsplit, L, W, (double*)out, ldo,
+                                                            scale);
+          else
+            split_reduce_kernel<float><<<nb, 256, 0, st>>>((const float*)dpart, dsplit, L, W, (float*)out, ldo,
+                                                           (float)scale);
+          SK_HIP(hipGetLastError());
+        }
+        return SK_OK;
+      }
+      if (split > 1) part = c->work;  // the workspace may have grown above
+    }
+  }
   if (h->dtype == SK_F64) {
     const double* A = (const double*)in->A;
     rc = trans ? dispatch<double, true>(c, cfg, A, in->lda, L, K, pass, (double*)out, ldo, scale, split,

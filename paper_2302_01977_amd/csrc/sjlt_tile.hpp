@@ -277,7 +277,8 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
 // dynamic LDS of one workgroup: the tile with its zero slot, then the entries
 inline size_t gather_lds_bytes(int esz, int kc, int tl, bool ldse, int nblk, int kcap) {
   const size_t ew = esz == 8 ? 16 : 8;
-  return (size_t)(kc + 1) * tl * esz + (ldse ? ((size_t)nblk * kcap + 4) * ew : 0);
+  // (+8 entries: the straight-line slots of the last bucket may read up to 7 past it)
+  return (size_t)(kc + 1) * tl * esz + (ldse ? ((size_t)nblk * kcap + 8) * ew : 0);
 }
 
 struct GatherCfg {
