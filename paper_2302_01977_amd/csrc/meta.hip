@@ -151,33 +151,84 @@ int launch_sjlt_meta_batch(const MetaItem* items, const int2* rows, int nrows, c
   return SK_OK;
 }
 
+// Fused generation of one block's tables: one workgroup per chunk of one table
+// set (S tables with chunk kc; optionally S' tables with chunk kct).  The
+// workgroup hashes its chunk's sources (the S set also writes the codes), then
+// counts, scans and scatters in LDS.  One launch replaces hash + count + scan +
+// scatter per set, which were dominated by launch gaps.
+struct MetaSet {
+  int32_t* ptr;
+  int32_t* ent;
+  int32_t kc, kcap, nT;
+};
+
+__global__ void __launch_bounds__(KC_MAX) sjlt_meta_fused(uint32_t* __restrict__ codes, int64_t n, int alpha,
+                                                          int w, uint32_t block, Key key, MetaSet s0, MetaSet s1) {
+  __shared__ uint32_t sc[KC_MAX * 32];
+  __shared__ int cnt[1025];
+  const bool first = (int)blockIdx.x < s0.nT;
+  const MetaSet& m = first ? s0 : s1;
+  const int t = first ? blockIdx.x : blockIdx.x - s0.nT;
+  const int kc = m.kc;
+  const int64_t k0 = (int64_t)t * kc;
+  const int nk = (int)min((int64_t)kc, n - k0);
+  const uint32_t wc = (uint32_t)(w / alpha);
+  // hash of the chunk's sources (same draws as hash_row)
+  for (int kk = threadIdx.x; kk < nk; kk += blockDim.x) {
+    const int64_t k = k0 + kk;
+    const uint32_t sbits = philox(2u, block, (uint32_t)k, 0u, key.k0, key.k1).v[0];
+    for (int c4 = 0; c4 < alpha; c4 += 4) {
+      const U4 o = philox(1u, block, (uint32_t)k, (uint32_t)(c4 >> 2), key.k0, key.k1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = c4 + q;
+        if (c < alpha) {
+          const uint32_t code = (((uint32_t)c * wc + mulhi(o.v[q], wc)) << 1) | ((sbits >> c) & 1u);
+          sc[kk * alpha + c] = code;
+          if (first) codes[k * alpha + c] = code;
+        }
+      }
+    }
+  }
+  for (int j = threadIdx.x; j <= w; j += blockDim.x) cnt[j] = 0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < nk * alpha; e += blockDim.x) atomicAdd(&cnt[sc[e] >> 1], 1);
+  __syncthreads();
+  // exclusive scan of the padded counts (thread 0, in order), offset by the region start
+  if (threadIdx.x == 0) {
+    int32_t run = (int32_t)t * m.kcap;
+    for (int j = 0; j < w; ++j) {
+      const int32_t c = cnt[j] + (cnt[j] & 1);
+      cnt[j] = run;
+      run += c;
+    }
+    cnt[w] = run;
+  }
+  for (int e = threadIdx.x; e < m.kcap; e += blockDim.x) m.ent[(int64_t)t * m.kcap + e] = kc << 1;  // nulls
+  __syncthreads();
+  for (int j = threadIdx.x; j <= w; j += blockDim.x) m.ptr[(int64_t)t * (w + 1) + j] = cnt[j];
+  const int kk = threadIdx.x;
+  if (kk < nk) {
+    for (int c = 0; c < alpha; ++c) {
+      const uint32_t code = sc[kk * alpha + c];
+      const uint32_t col = code >> 1;
+      int rank = 0;
+      for (int q = 0; q < kk; ++q) rank += (sc[q * alpha + c] >> 1) == col;
+      m.ent[cnt[col] + rank] = (kk << 1) | (int)(code & 1u);
+    }
+  }
+}
+
 int launch_sjlt_meta(Handle* h, Block& b, hipStream_t st) {
   const int64_t n = h->n;
-  const int kc = h->kc;
-  const int nT = (int)((n + kc - 1) / kc);
-  const uint32_t wc = (uint32_t)(b.w / h->alpha);
-  const Key key = key_of(h->seed);
+  SK_REQUIRE(b.w <= 1024 && (int64_t)h->alpha * KC_MAX <= KC_MAX * 32, SK_EINVAL, "block too wide for the tables");
+  MetaSet s0{b.ptr, b.ent, h->kc, sjlt_kcap(h->kc, h->alpha, b.w), (int)((n + h->kc - 1) / h->kc)};
+  MetaSet s1{nullptr, nullptr, 64, 0, 0};
+  if (b.ptr_t) s1 = MetaSet{b.ptr_t, b.ent_t, h->kct, sjlt_kcap(h->kct, h->alpha, b.w), (int)((n + h->kct - 1) / h->kct)};
   ProfScope ps(h->ctx, "sjlt_meta", st);
-  sjlt_hash_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(b.codes, n, h->alpha, wc, (uint32_t)b.index, key);
+  sjlt_meta_fused<<<s0.nT + s1.nT, KC_MAX, 0, st>>>(b.codes, n, h->alpha, b.w, (uint32_t)b.index, key_of(h->seed),
+                                                     s0, s1);
   SK_HIP(hipGetLastError());
-  sjlt_count_kernel<<<nT, 256, 0, st>>>(b.codes, b.ptr, n, h->alpha, b.w, kc);
-  SK_HIP(hipGetLastError());
-  const int kcap = sjlt_kcap(kc, h->alpha, b.w);
-  chunk_scan_kernel<<<nT, 64, 0, st>>>(b.ptr, b.w, kcap);
-  SK_HIP(hipGetLastError());
-  sjlt_scatter_kernel<<<nT, kc, 0, st>>>(b.codes, b.ptr, b.ent, n, h->alpha, b.w, kc, kcap);
-  SK_HIP(hipGetLastError());
-  if (b.ptr_t) {  // S' tables with their own chunk size
-    const int kt = h->kct;
-    const int nTt = (int)((n + kt - 1) / kt);
-    const int kcapt = sjlt_kcap(kt, h->alpha, b.w);
-    sjlt_count_kernel<<<nTt, 256, 0, st>>>(b.codes, b.ptr_t, n, h->alpha, b.w, kt);
-    SK_HIP(hipGetLastError());
-    chunk_scan_kernel<<<nTt, 64, 0, st>>>(b.ptr_t, b.w, kcapt);
-    SK_HIP(hipGetLastError());
-    sjlt_scatter_kernel<<<nTt, kt, 0, st>>>(b.codes, b.ptr_t, b.ent_t, n, h->alpha, b.w, kt, kcapt);
-    SK_HIP(hipGetLastError());
-  }
   return SK_OK;
 }
 
