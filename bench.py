@@ -43,8 +43,8 @@ BF16_PEAK_TFLOPS = 2500.0
 # VALU issue without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 # the dominant kernel's sources: the traffic figures below are valid only for them
-GATHER_SOURCES = ("paper_2302_01977_amd/csrc/sjlt.hip", "paper_2302_01977_amd/csrc/sjlt_tile.hpp",
-                  "paper_2302_01977_amd/csrc/gather.hpp")
+GATHER_SOURCES = ("paper_2302_01977_amd/csrc/sjlt.hip", "paper_2302_01977_amd/csrc/sjlt_dma.hip",
+                  "paper_2302_01977_amd/csrc/sjlt_tile.hpp", "paper_2302_01977_amd/csrc/gather.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sjlt_gather_cauchy16k_traffic.txt")
 
 
@@ -338,7 +338,7 @@ def main():
         traffic = recorded_traffic()
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "sjlt_gather_kernel (S = A R)", "bytes_per_launch": bytes_sketch,
+                "kernel": "sjlt_dma_kernel (S = A R, direct-to-LDS)", "bytes_per_launch": bytes_sketch,
                 "avg_launch_ms": g["avg_ms"], "frac_of_measured_copy": round(ach / copy_gbps, 4),
                 "source_digest": sources_digest()}
     for sk in sketches.values():

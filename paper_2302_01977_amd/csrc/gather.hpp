@@ -70,8 +70,8 @@ namespace sk {
 // a data-dependent loop per column leaves one dependent chain of LDS reads in
 // flight.  So the first ms (4 or 8) slots of every bucket are gathered by
 // straight-line code (slots past the bucket's end read the zero row at zaddr),
-// four independent reads at a time; the rest of a longer bucket (even length)
-// follows in pairs.
+// four independent reads at a time; the rest of a longer bucket follows in
+// pairs (and a last single entry).
 template <typename T, int NJ, int RPL, typename VT>
 __device__ __forceinline__ void gather_chunk_lds(const uint32_t* E, int ebase, uint32_t bnd, uint32_t bndN,
                                                  uint32_t lane_part, uint32_t zaddr, int ms,
@@ -117,7 +117,8 @@ __device__ __forceinline__ void gather_chunk_lds(const uint32_t* E, int ebase, u
     };
     four(0);
     if (ms > 4) four(4);  // buckets of about eight entries: eight straight-line slots
-    for (int e = e0 + ms; e < e1; e += 2) {
+    int e = e0 + ms;
+    for (; e + 1 < e1; e += 2) {
       uint32_t a0, a1;
       T s0, s1;
       entry(e, a0, s0);
@@ -125,6 +126,14 @@ __device__ __forceinline__ void gather_chunk_lds(const uint32_t* E, int ebase, u
       const VT x0 = *(lds_vt)(uintptr_t)a0, x1 = *(lds_vt)(uintptr_t)a1;
 #pragma unroll
       for (int r = 0; r < RPL; ++r) acc[jj][r] = fma(((const T*)&x1)[r], s1, fma(((const T*)&x0)[r], s0, acc[jj][r]));
+    }
+    if (e < e1) {  // odd bucket length
+      uint32_t a0;
+      T s0;
+      entry(e, a0, s0);
+      const VT x0 = *(lds_vt)(uintptr_t)a0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[jj][r] = fma(((const T*)&x0)[r], s0, acc[jj][r]);
     }
   }
 }
@@ -174,7 +183,8 @@ __device__ __forceinline__ void gather_chunk_lds_ms(const uint32_t* E, int ebase
         acc[jj][r] = a;
       }
     }
-    for (int e = e0 + MS; e < e1; e += 2) {
+    int e = e0 + MS;
+    for (; e + 1 < e1; e += 2) {
       uint32_t a0, a1;
       T s0, s1;
       entry(e, a0, s0);
@@ -182,6 +192,14 @@ __device__ __forceinline__ void gather_chunk_lds_ms(const uint32_t* E, int ebase
       const VT x0 = *(lds_vt)(uintptr_t)a0, x1 = *(lds_vt)(uintptr_t)a1;
 #pragma unroll
       for (int r = 0; r < RPL; ++r) acc[jj][r] = fma(((const T*)&x1)[r], s1, fma(((const T*)&x0)[r], s0, acc[jj][r]));
+    }
+    if (e < e1) {  // odd bucket length
+      uint32_t a0;
+      T s0;
+      entry(e, a0, s0);
+      const VT x0 = *(lds_vt)(uintptr_t)a0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[jj][r] = fma(((const T*)&x0)[r], s0, acc[jj][r]);
     }
   }
 }

@@ -114,9 +114,11 @@ struct SjltPass {
 };
 
 // Entry slots reserved per chunk of one block: the chunk's KC * alpha entries,
-// plus one null entry for each bucket of odd length (buckets are padded to even
-// length), rounded up to 256 so that chunk regions start on 1 KB boundaries.
-inline int sjlt_kcap(int kc, int alpha, int w) { return (kc * alpha + w + 255) / 256 * 256; }
+// rounded up to 256 so that chunk regions start on 1 KB boundaries.
+inline int sjlt_kcap(int kc, int alpha, int w) {
+  (void)w;
+  return (kc * alpha + 255) / 256 * 256;
+}
 
 // One SJLT operator block to generate in a batched launch.
 struct MetaItem {

@@ -34,10 +34,9 @@ __global__ void __launch_bounds__(256) sjlt_hash_kernel(uint32_t* __restrict__ c
 
 // Bucket table, chunk-major: ptr[t * (w + 1) + j] = first entry of column j in
 // chunk t; slot w holds the end of the chunk's entries.  Chunk t owns the entry
-// slots [t * kcap, (t + 1) * kcap).  Every bucket is padded to an even length
-// with a null entry (source KC, sign +), which the gather kernels map to a
-// staged source slot of zeros; unused slots of the region hold null entries too.
-// count_chunk stores the padded counts, scan_chunk turns them into starts.
+// slots [t * kcap, (t + 1) * kcap); its unused slots hold null entries (source
+// KC, sign +, a staged slot of zeros).  count_chunk stores the counts,
+// scan_chunk turns them into starts.
 __device__ __forceinline__ void count_chunk(const uint32_t* __restrict__ codes, int32_t* __restrict__ ptr,
                                             int64_t n, int alpha, int w, int kc, int t, int* cnt) {
   for (int j = threadIdx.x; j < w; j += blockDim.x) cnt[j] = 0;
@@ -47,7 +46,7 @@ __device__ __forceinline__ void count_chunk(const uint32_t* __restrict__ codes, 
   for (int e = threadIdx.x; e < nk * alpha; e += blockDim.x) atomicAdd(&cnt[codes[k0 * alpha + e] >> 1], 1);
   __syncthreads();
   for (int j = threadIdx.x; j <= w; j += blockDim.x)
-    ptr[(int64_t)t * (w + 1) + j] = j < w ? cnt[j] + (cnt[j] & 1) : 0;
+    ptr[(int64_t)t * (w + 1) + j] = j < w ? cnt[j] : 0;
 }
 
 __global__ void __launch_bounds__(256) sjlt_count_kernel(const uint32_t* __restrict__ codes,
@@ -57,7 +56,7 @@ __global__ void __launch_bounds__(256) sjlt_count_kernel(const uint32_t* __restr
   count_chunk(codes, ptr, n, alpha, w, kc, blockIdx.x, cnt);
 }
 
-// Exclusive scan of chunk t's w + 1 padded counts, offset by the chunk's region
+// Exclusive scan of chunk t's w + 1 counts, offset by the chunk's region
 // start (thread 0 walks the row in order).
 __device__ __forceinline__ void scan_chunk(int32_t* __restrict__ ptr, int w, int kcap, int t) {
   if (threadIdx.x != 0) return;
@@ -194,11 +193,11 @@ __global__ void __launch_bounds__(KC_MAX) sjlt_meta_fused(uint32_t* __restrict__
   __syncthreads();
   for (int e = threadIdx.x; e < nk * alpha; e += blockDim.x) atomicAdd(&cnt[sc[e] >> 1], 1);
   __syncthreads();
-  // exclusive scan of the padded counts (thread 0, in order), offset by the region start
+  // exclusive scan of the counts (thread 0, in order), offset by the region start
   if (threadIdx.x == 0) {
     int32_t run = (int32_t)t * m.kcap;
     for (int j = 0; j < w; ++j) {
-      const int32_t c = cnt[j] + (cnt[j] & 1);
+      const int32_t c = cnt[j];
       cnt[j] = run;
       run += c;
     }

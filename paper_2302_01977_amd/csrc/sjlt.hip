@@ -160,9 +160,11 @@ static DmaShape choose_dma(int dtype, int kc, int W, int g, int nblk, int kcap) 
 
 // Chunk sizes of a dense operator of width d.  S: about two entries per bucket
 // when the direct-to-LDS kernel has a shape for it (it double-buffers the tile,
-// so shorter chunks keep it in LDS), else about four.  S': about four in FP64,
-// two in FP32 (register-staged kernel, measured on MI355X).  kct = 0 when S'
-// shares the S tables.
+// so shorter chunks keep it in LDS), else about four.  S' (register-staged
+// kernel): about four in FP64, two in FP32.  A direct-to-LDS S' kernel was
+// measured slower on MI355X: a lane's sources run down one column of A, and the
+// double-buffered tile limits those runs to 1 KB.  kct = 0 when S' shares the
+// S tables.
 void sjlt_pick_chunks(int dtype, int d, int alpha, bool want_t, int* kc, int* kct) {
   const int k2 = sjlt_chunk_for(d, alpha, 2);
   *kc = choose_dma(dtype, k2, d, d, 1, sjlt_kcap(k2, alpha, d)).nw ? k2 : sjlt_chunk_for(d, alpha, 4);
@@ -282,8 +284,8 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
   int rc;
   // S with whole-workgroup column coverage: the direct-to-LDS kernel when a
   // shape fits (it splits the source range by the same rule)
-  if (!trans) {
-    DmaShape ds = choose_dma(h->dtype, kc, W, g, nblk, pass.kcap);
+  {
+    DmaShape ds = trans ? DmaShape{0, 0, 0} : choose_dma(h->dtype, kc, W, g, nblk, pass.kcap);
     if (ds.nw) {
       const size_t dbytes = dma_lds_bytes((int)esz, kc, 64 * ds.rpl, nblk, pass.kcap);
       const int64_t dtiles = (L + 64 * ds.rpl - 1) / (64 * ds.rpl);
@@ -306,8 +308,8 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
         if ((rc = ensure_work(c, (size_t)dsplit * (size_t)L * (size_t)W * esz))) return rc;
         dpart = c->work;
       }
-      rc = launch_sjlt_dma(c, h->dtype, ds.nw, ds.nj, ds.rpl, kc, in->A, in->lda, L, K, dp, out, ldo, scale,
-                           dsplit, dpart, 1, st);
+      rc = launch_sjlt_dma(c, h->dtype, ds.nw, ds.nj, ds.rpl, kc, in->A, in->lda, L, K, dp, out, ldo, scale, dsplit,
+                           dpart, 1, st);
       if (rc != 1) {
         if (rc) return rc;
         if (dsplit > 1) {
