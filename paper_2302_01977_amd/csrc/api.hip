@@ -356,6 +356,7 @@ int sketch_apply(sk_ctx* ctx, const sk_input* in, const sk_op_desc* op, int32_t 
   }
   int rc = validate_width(h, d);
   if (!rc && h->kind == SK_SRHT) rc = dev_alloc(&h->srht_D, (size_t)h->n);
+  if (!rc && h->kind == SK_SRHT) rc = dev_alloc(&h->srht_Db, (size_t)((h->n + 255) / 256 * 8));
   if (!rc && h->kind == SK_SRHT) {
     if (h->dtype == SK_F64) rc = dev_alloc((double**)&h->srht_Dv, (size_t)h->n);
     else rc = dev_alloc((float**)&h->srht_Dv, (size_t)h->n);
@@ -369,6 +370,7 @@ int sketch_apply(sk_ctx* ctx, const sk_input* in, const sk_op_desc* op, int32_t 
     for (auto& b : h->blocks) free_block(b);
     if (h->srht_D) (void)hipFree(h->srht_D);
     if (h->srht_Dv) (void)hipFree(h->srht_Dv);
+    if (h->srht_Db) (void)hipFree(h->srht_Db);
     if (h->srht_mu) (void)hipFree(h->srht_mu);
     h->magic = 0;
     delete H;
@@ -450,6 +452,7 @@ int sketch_release(sk_handle* H) {
   for (auto& b : h->blocks) free_block(b);
   if (h->srht_D) (void)hipFree(h->srht_D);
   if (h->srht_Dv) (void)hipFree(h->srht_Dv);
+  if (h->srht_Db) (void)hipFree(h->srht_Db);
   if (h->srht_mu) (void)hipFree(h->srht_mu);
   h->ctx->live_handles--;
   h->magic = 0;

@@ -94,6 +94,8 @@ struct Handle {
   // SRHT
   int8_t* srht_D = nullptr;     // n signs (+1 / -1)
   void* srht_Dv = nullptr;      // the same signs as +-1.0 in the element type
+  uint32_t* srht_Db = nullptr;  // the same signs as bits (bit k % 32 of word k / 32 set when D_k = -1),
+                                // words for roundup(n, 256) sources (zero past n)
   uint32_t* srht_mu = nullptr;  // capacity mu_cap
   int32_t mu_cap = 0;
 };
@@ -151,6 +153,14 @@ int launch_sjlt_adjoint(Handle* h, const sk_input* in, int b0, int b1, const voi
                         int64_t lddA, hipStream_t st);
 void split_reduce_f32(const float* part, int split, int64_t L, int64_t W, float* out, int64_t ldo, float scale,
                       hipStream_t st);
+// out(:, j) = scale * sum_s part[s](:, j) for the split-source partials (L x W each, packed)
+void split_reduce_any(int dtype, const void* part, int split, int64_t L, int64_t W, void* out, int64_t ldo,
+                      double scale, hipStream_t st);
+// SRHT S = A D H P (trans: S' = A^T D H P) with direct-to-LDS loads; returns 1
+// when A's alignment rules them out
+int launch_srht_dma(Ctx* c, int dtype, bool trans, const void* A, int64_t lda, int64_t L, int64_t K,
+                    const uint32_t* Db, const uint32_t* mu, int64_t col0, int W, void* out, int64_t ldo, double scale,
+                    hipStream_t st);
 
 int launch_sjlt_dma(Ctx* c, int dtype, int nw, int nj, int rpl, int kc, const void* A, int64_t lda, int64_t L,
                     int64_t K, const SjltPass& pass, void* out, int64_t ldo, double scale, int split, void* part,

@@ -240,6 +240,18 @@ __global__ void __launch_bounds__(256) srht_D_kernel(int8_t* __restrict__ D, T* 
   Dv[k] = neg ? T(-1) : T(1);
 }
 
+// word q of the sign bits: bit b set when D_{32 q + b} = -1 (zero past n)
+__global__ void __launch_bounds__(256) srht_Db_kernel(uint32_t* __restrict__ Db, int64_t nwords, int64_t n, Key key) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nwords) return;
+  uint32_t w = 0;
+  for (int b = 0; b < 32; ++b) {
+    const int64_t k = 32 * q + b;
+    if (k < n && srht_neg(key, (uint32_t)k)) w |= 1u << b;
+  }
+  Db[q] = w;
+}
+
 __global__ void __launch_bounds__(256) srht_mu_kernel(uint32_t* __restrict__ mu, int64_t j0, int64_t j1,
                                                       uint32_t nu, Key key) {
   const int64_t j = j0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -252,6 +264,9 @@ int launch_srht_meta(Handle* h, int64_t j0, int64_t j1, bool draw_D, hipStream_t
     const unsigned nb = (unsigned)((h->n + 255) / 256);
     if (h->dtype == SK_F64) srht_D_kernel<double><<<nb, 256, 0, st>>>(h->srht_D, (double*)h->srht_Dv, h->n, key);
     else srht_D_kernel<float><<<nb, 256, 0, st>>>(h->srht_D, (float*)h->srht_Dv, h->n, key);
+    SK_HIP(hipGetLastError());
+    const int64_t nwords = (h->n + 255) / 256 * 8;
+    srht_Db_kernel<<<(unsigned)((nwords + 255) / 256), 256, 0, st>>>(h->srht_Db, nwords, h->n, key);
     SK_HIP(hipGetLastError());
   }
   if (j1 > j0) {

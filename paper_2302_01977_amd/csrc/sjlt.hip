@@ -56,6 +56,15 @@ void split_reduce_f32(const float* part, int split, int64_t L, int64_t W, float*
   split_reduce_kernel<float><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(part, split, L, W, out, ldo, scale);
 }
 
+void split_reduce_any(int dtype, const void* part, int split, int64_t L, int64_t W, void* out, int64_t ldo,
+                      double scale, hipStream_t st) {
+  const unsigned nb = (unsigned)((L * W + 255) / 256);
+  if (dtype == SK_F64)
+    split_reduce_kernel<double><<<nb, 256, 0, st>>>((const double*)part, split, L, W, (double*)out, ldo, scale);
+  else
+    split_reduce_kernel<float><<<nb, 256, 0, st>>>((const float*)part, split, L, W, (float*)out, ldo, (float)scale);
+}
+
 // ------------------------------------------------------------------ dispatch
 template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK, bool LDSE>
 static int run_gather(Ctx* c, const T* A, int64_t lda, int64_t L, int64_t K, const SjltPass& pass, T* out,
@@ -285,7 +294,9 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
   // S with whole-workgroup column coverage: the direct-to-LDS kernel when a
   // shape fits (it splits the source range by the same rule)
   {
-    DmaShape ds = trans ? DmaShape{0, 0, 0} : choose_dma(h->dtype, kc, W, g, nblk, pass.kcap);
+    // (direct-to-LDS 16-byte loads: A and its columns 16-byte aligned)
+    const bool al16 = (uintptr_t)in->A % 16 == 0 && (in->lda * (int64_t)esz) % 16 == 0;
+    DmaShape ds = trans || !al16 ? DmaShape{0, 0, 0} : choose_dma(h->dtype, kc, W, g, nblk, pass.kcap);
     if (ds.nw) {
       const size_t dbytes = dma_lds_bytes((int)esz, kc, 64 * ds.rpl, nblk, pass.kcap);
       const int64_t dtiles = (L + 64 * ds.rpl - 1) / (64 * ds.rpl);

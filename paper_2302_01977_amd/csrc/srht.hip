@@ -155,8 +155,11 @@ int launch_srht_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
     for (int q = b; q < e; ++q) W += h->blocks[q].w;
     const double scale = 1.0 / sqrt((double)h->blocks[b].w);
     char* o = (char*)out + (size_t)col * ldo * esz;
-    int rc;
-    if (h->dtype == SK_F64) {
+    int rc = launch_srht_dma(h->ctx, h->dtype, trans, in->A, in->lda, L, K, h->srht_Db, h->srht_mu,
+                             h->blocks[b].col0, W, o, ldo, scale, st);
+    if (rc != 1) {
+      if (rc) return rc;
+    } else if (h->dtype == SK_F64) {
       rc = trans ? srht_dispatch<double, true>(h->ctx, W, (const double*)in->A, in->lda, L, K,
                                                (const double*)h->srht_Dv, h->srht_mu, h->blocks[b].col0,
                                                (double*)o, ldo, scale, st)

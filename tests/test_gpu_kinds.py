@@ -56,6 +56,46 @@ def test_srht_parity(ctx, dtype, m, n, w):
     sk.release()
 
 
+def _padded_colmajor(A, ld, dtype):
+    """Device column-major copy of A whose leading dimension is ld >= rows."""
+    m, n = A.shape
+    buf = torch.zeros((n, ld), dtype=dtype, device="cuda")
+    buf[:, :m] = torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda")
+    return buf.t()[:m, :]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("m,n,ld,w", [(2048, 2048, 2048, 320),   # two column slices per row tile
+                                      (1030, 1024, 1031, 64),    # odd lda: 16-byte loads ruled out
+                                      (1030, 1024, 1032, 96),    # padded lda, ragged row tile
+                                      (64, 8192, 64, 128)])      # one row tile: source range split
+def test_srht_load_paths(ctx, dtype, m, n, ld, w):
+    """S and S' against the explicit operator (eq. for R = D H P, section 2.4.2)
+    across the launch shapes: wide passes, leading dimensions that rule the
+    direct-to-LDS loads in or out, and a split source range."""
+    api = _api()
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    A = workloads.random_dense(m, n, 31, dtype)
+    Ad = _padded_colmajor(A, ld, tdt)
+    sk = api.Sketch(ctx, Ad, "srht", w, 45)
+    torch.cuda.synchronize()
+    A64 = A.astype(np.float64)
+    R = ops.srht_block(n, w, 0, 45)
+    tol = 1e-12 if dtype == np.float64 else 1e-5
+    assert osk.rel_fro(sk.S.cpu().numpy(), A64 @ R) <= tol
+    sk.release()
+    if m >= n:
+        # S' of the leading n x n block: the rows of A are the sources
+        At = A[:n, :]
+        sq = _padded_colmajor(At, ld, tdt)
+        sk = api.Sketch(ctx, sq, "srht", w, 46, transpose=True)
+        torch.cuda.synchronize()
+        R = ops.srht_block(n, w, 0, 46)
+        assert osk.rel_fro(sk.St.cpu().numpy(), At.astype(np.float64).T @ R) <= tol
+        assert osk.rel_fro(sk.S.cpu().numpy(), At.astype(np.float64) @ R) <= tol
+        sk.release()
+
+
 def test_srht_extension_and_identity(ctx):
     api = _api()
     n = 256
