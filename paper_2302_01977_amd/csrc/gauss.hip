@@ -10,7 +10,7 @@
 //   FP32 inputs are promoted on load, so this is also the FP64 reference for FP32 A.
 // gauss_bf16_kernel: v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  The 16x32
 //   A fragment needs 8 consecutive k per row while A is column-major, so each
-//   64 x 64 chunk of A is loaded in 4x4 blocks, rounded to bf16 (and, for
+//   128 x 32 step of A is loaded in 4x4 blocks, rounded to bf16 (and, for
 //   bf16x3, split exactly a = a1 + a2 + a3 into three bf16 parts), transposed in
 //   registers and written to LDS rows of k (padded rows: conflict-free reads).
 #include <algorithm>
@@ -99,115 +99,191 @@ __global__ void __launch_bounds__(256)
 }
 
 // ------------------------------------------------------------------- BF16
+// A workgroup of 4 waves owns 128 rows of the result and up to 256 of its
+// columns; wave q computes rows 32 q .. 32 q + 31 (two 16-row blocks, so every R
+// fragment read from LDS feeds two MFMAs per part).  The source range is walked
+// in steps of 32 (one MFMA depth) and split across workgroups (partial sums
+// reduced in a fixed order) so that the row tiles fill the chip and the slice of
+// R that one workgroup reads fits an XCD's L2: workgroups are dealt to the 8 XCDs
+// in turn, so the launch gives every source slice its own XCDs and R is read
+// from HBM about once per XCD.  Step kt + 1 of A and R is loaded into registers
+// while step kt is multiplied.
+struct Bf16Grid {
+  int64_t tiles;  // row tiles x column slices
+  int gz;         // column slices
+  int split;      // source slices
+  int xcd;        // 1: source slice s runs on XCDs [s 8 / split, (s + 1) 8 / split)
+};
+
 template <int NB, bool X3, bool TRANS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     gauss_bf16_kernel(const float* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                       const uint16_t* __restrict__ g, int64_t ldg, int W, float* __restrict__ S, int64_t ldS,
-                      float scale) {
-  constexpr int KT = 64;
+                      float scale, Bf16Grid gr, float* __restrict__ part) {
+  constexpr int KT = 32;
+  constexpr int RS = KT + 8;  // padded LDS row (bf16 elements): 80 bytes, conflict-free 16-byte reads
+  constexpr int MR = 128;
   constexpr int NP = X3 ? 3 : 1;
-  constexpr int RS = KT + 8;  // padded row length (bf16 elements): 144 bytes
   constexpr int WP = NB * 16;
-  __shared__ __attribute__((aligned(16))) __bf16 At[NP][64 * RS];
+  constexpr int NPIECE = WP * KT / 8;  // 16-byte pieces of the R step
+  constexpr int RV = (NPIECE + 255) / 256;
+  __shared__ __attribute__((aligned(16))) __bf16 At[NP][MR * RS];
   __shared__ __attribute__((aligned(16))) __bf16 Rt[WP * RS];
+  // work item of this workgroup
+  const int64_t lin = blockIdx.x;
+  int64_t tile;
+  int s;
+  if (gr.xcd) {
+    const int per = 8 / gr.split;  // XCDs per source slice
+    const int x = (int)(lin & 7);
+    s = x / per;
+    tile = (x % per) + per * (lin >> 3);
+  } else {
+    s = (int)(lin / gr.tiles);
+    tile = lin % gr.tiles;
+  }
+  if (tile >= gr.tiles) return;  // whole workgroup: no barrier is reached
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int q = tid >> 6;
-  const int64_t rowblk = (int64_t)blockIdx.x * 64;
-  const int jbase = blockIdx.z * WP;
-  const int wloc = std::min(WP, W - jbase);
   const int lr = lane & 15, lk = lane >> 4;
+  const int64_t row0 = (tile / gr.gz) * MR;
+  const int jbase = (int)(tile % gr.gz) * WP;
+  const int wloc = std::min(WP, W - jbase);
+  const int64_t nK = (n + KT - 1) / KT;
+  const int64_t kt0 = nK * s / gr.split, kt1 = nK * (s + 1) / gr.split;
+  const bool g16 = (ldg & 7) == 0 && ((uintptr_t)g & 15) == 0;  // R pieces are 16-byte aligned
 
-  // A staging: thread -> 4x4 block (rows 4*rb.., columns 4*cb..)
-  const int rb = tid >> 4, cbk = tid & 15;  // 16 row blocks x 16 column blocks
-  const int64_t ar0 = rowblk + 4 * rb;
-  f4 acc[NB];
-#pragma unroll
-  for (int cb = 0; cb < NB; ++cb) acc[cb] = f4{0.f, 0.f, 0.f, 0.f};
+  // staging roles.  S: a 4 x 4 block (rows 4 rg.., sources 4 kg..) transposed in
+  // registers.  S' (A^T): row rt, sources 16 ht .. 16 ht + 15 (contiguous in A).
+  const int rg = tid & 31, kg = tid >> 5;
+  const int rt = tid & 127, ht = tid >> 7;
+  float areg[4][4];
+  uint32_t rreg[RV][4];
 
-  for (int64_t k0 = 0; k0 < n; k0 += KT) {
-    float a[4][4];  // [column][row]
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t k = k0 + 4 * cbk + c;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = ar0 + r;
-        a[c][r] = (row < m && k < n) ? aelem<TRANS>(A, lda, row, k) : 0.f;
-      }
-    }
-    // R chunk: WP columns x KT k, thread -> (column, 8 consecutive k)
-    constexpr int RV = WP * KT / 8 / 256;  // 16-byte pieces per thread (>= 1 for WP >= 32)
-    uint32_t rpiece[RV > 0 ? RV : 1][4];
-#pragma unroll
-    for (int u = 0; u < (RV > 0 ? RV : 1); ++u) {
-      const int pid = u * 256 + tid;
-      const int j = pid / (KT / 8), kk = (pid % (KT / 8)) * 8;
-      uint16_t hv[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t k = k0 + kk + e;
-        hv[e] = (pid < WP * KT / 8 && j < wloc && k < n) ? g[k + (int64_t)(jbase + j) * ldg] : (uint16_t)0;
-      }
-      __builtin_memcpy(rpiece[u], hv, 16);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      __bf16 p1[4], p2[4], p3[4];
+  auto load_step = [&](int64_t kt) {
+    const int64_t k0 = kt * KT;
+    if (!TRANS) {
+      const int64_t r = row0 + 4 * rg;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const float x = a[c][r];
-        const __bf16 h1 = (__bf16)x;
-        p1[c] = h1;
-        if (X3) {
-          const float r1 = x - (float)h1;
-          const __bf16 h2 = (__bf16)r1;
-          p2[c] = h2;
-          p3[c] = (__bf16)(r1 - (float)h2);
+        const int64_t k = k0 + 4 * kg + c;
+        const float* p = A + r + k * lda;
+        if (k < n && r + 4 <= m) {
+          __builtin_memcpy(areg[c], p, 16);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) areg[c][e] = (k < n && r + e < m) ? p[e] : 0.f;
         }
       }
-      const int off = (4 * rb + r) * RS + 4 * cbk;
-      __builtin_memcpy(&At[0][off], p1, 8);
-      if (X3) {
-        __builtin_memcpy(&At[1 % NP][off], p2, 8);
-        __builtin_memcpy(&At[2 % NP][off], p3, 8);
+    } else {
+      const int64_t r = row0 + rt;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t k = k0 + 16 * ht + 4 * u;
+        const float* p = A + k + r * lda;
+        if (r < m && k + 4 <= n) {
+          __builtin_memcpy(areg[u], p, 16);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) areg[u][e] = (r < m && k + e < n) ? p[e] : 0.f;
+        }
       }
     }
 #pragma unroll
-    for (int u = 0; u < (RV > 0 ? RV : 1); ++u) {
+    for (int u = 0; u < RV; ++u) {
       const int pid = u * 256 + tid;
-      if (pid < WP * KT / 8) {
-        const int j = pid / (KT / 8), kk = (pid % (KT / 8)) * 8;
-        __builtin_memcpy(&Rt[j * RS + kk], rpiece[u], 16);
+      const int j = pid >> 2, kk = (pid & 3) * 8;
+      const int64_t k = k0 + kk;
+      const uint16_t* p = g + k + (int64_t)(jbase + j) * ldg;
+      if (pid < NPIECE && j < wloc && g16 && k + 8 <= n) {
+        __builtin_memcpy(rreg[u], p, 16);
+      } else {
+        uint16_t hv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) hv[e] = (pid < NPIECE && j < wloc && k + e < n) ? p[e] : (uint16_t)0;
+        __builtin_memcpy(rreg[u], hv, 16);
       }
     }
+  };
+
+  auto split_store = [&](const float (&x)[4], int off) {
+    __bf16 p1[4], p2[4], p3[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const __bf16 h1 = (__bf16)x[e];
+      p1[e] = h1;
+      if (X3) {
+        const float r1 = x[e] - (float)h1;
+        const __bf16 h2 = (__bf16)r1;
+        p2[e] = h2;
+        p3[e] = (__bf16)(r1 - (float)h2);
+      }
+    }
+    __builtin_memcpy(&At[0][off], p1, 8);
+    if (X3) {
+      __builtin_memcpy(&At[1 % NP][off], p2, 8);
+      __builtin_memcpy(&At[2 % NP][off], p3, 8);
+    }
+  };
+
+  f4 acc[2][NB];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+
+  if (kt0 < kt1) load_step(kt0);
+  for (int64_t kt = kt0; kt < kt1; ++kt) {
+    __syncthreads();  // the previous step's fragments are read
+    if (!TRANS) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float x[4] = {areg[0][r], areg[1][r], areg[2][r], areg[3][r]};
+        split_store(x, (4 * rg + r) * RS + 4 * kg);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) split_store(areg[u], rt * RS + 16 * ht + 4 * u);
+    }
+#pragma unroll
+    for (int u = 0; u < RV; ++u) {
+      const int pid = u * 256 + tid;
+      if (pid < NPIECE) __builtin_memcpy(&Rt[(pid >> 2) * RS + (pid & 3) * 8], rreg[u], 16);
+    }
+    if (kt + 1 < kt1) load_step(kt + 1);
     __syncthreads();
+    bf8 af[2][NP];
 #pragma unroll
-    for (int ks = 0; ks < KT / 32; ++ks) {
-      bf8 af[NP];
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int p = 0; p < NP; ++p) __builtin_memcpy(&af[p], &At[p][(16 * q + lr) * RS + 32 * ks + 8 * lk], 16);
+      for (int p = 0; p < NP; ++p) __builtin_memcpy(&af[rb][p], &At[p][(32 * q + 16 * rb + lr) * RS + 8 * lk], 16);
 #pragma unroll
-      for (int cb = 0; cb < NB; ++cb) {
-        bf8 bfr;
-        __builtin_memcpy(&bfr, &Rt[(cb * 16 + lr) * RS + 32 * ks + 8 * lk], 16);
+    for (int cb = 0; cb < NB; ++cb) {
+      bf8 bfr;
+      __builtin_memcpy(&bfr, &Rt[(cb * 16 + lr) * RS + 8 * lk], 16);
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int p = NP - 1; p >= 0; --p)  // small parts first
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[p], bfr, acc[cb], 0, 0, 0);
-      }
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[rb][p], bfr, acc[rb][cb], 0, 0, 0);
     }
   }
+  float* dst = gr.split > 1 ? part + (int64_t)s * m * W : S;
+  const int64_t ldd = gr.split > 1 ? m : ldS;
+  const float sc = gr.split > 1 ? 1.f : scale;
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) {
     const int j = jbase + cb * 16 + lr;
     if (j >= W) continue;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      // v_mfma_f32_16x16x32_bf16 returns D[4 (lane / 16) + v][lane % 16] in item v
-      const int64_t r = rowblk + 16 * q + 4 * lk + v;
-      if (r < m) S[r + (int64_t)j * ldS] = acc[cb][v] * scale;
-    }
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // v_mfma_f32_16x16x32_bf16 returns D[4 (lane / 16) + v][lane % 16] in item v
+        const int64_t r = row0 + 32 * q + 16 * rb + 4 * lk + v;
+        if (r < m) dst[r + (int64_t)j * ldd] = acc[rb][cb][v] * sc;
+      }
   }
 }
 
@@ -234,17 +310,48 @@ static int run_bf16(Ctx* c, bool x3, const float* A, int64_t lda, int64_t m, int
                     float* S, int64_t ldS, float scale, hipStream_t st) {
   const int nb = std::min(16, (W + 15) / 16);
   const int nbk = nb <= 2 ? 2 : nb <= 4 ? 4 : nb <= 8 ? 8 : 16;
-  const int gz = (W + nbk * 16 - 1) / (nbk * 16);
-  dim3 grid((unsigned)((m + 63) / 64), 1, (unsigned)gz);
-  ProfScope ps(c, x3 ? (TRANS ? "gauss_bf16x3_t" : "gauss_bf16x3") : (TRANS ? "gauss_bf16_t" : "gauss_bf16"), st);
-#define SK_BF_CASE(NB_)                                                                                      \
-  if (nbk == NB_) {                                                                                          \
-    if (x3) gauss_bf16_kernel<NB_, true, TRANS><<<grid, 256, 0, st>>>(A, lda, m, n, g, n, W, S, ldS, scale); \
-    else gauss_bf16_kernel<NB_, false, TRANS><<<grid, 256, 0, st>>>(A, lda, m, n, g, n, W, S, ldS, scale);  \
+  Bf16Grid gr;
+  gr.gz = (W + nbk * 16 - 1) / (nbk * 16);
+  gr.tiles = ((m + 127) / 128) * gr.gz;
+  // source slices: enough for about two workgroups per CU, and for the slice of
+  // R (n x W bf16) read on one XCD to take at most half of its 4 MB L2; a power
+  // of two up to 8 (then each slice owns whole XCDs), at least 8 steps each
+  const int64_t nK = (n + 31) / 32;
+  const double rbytes = 2.0 * (double)n * (double)std::min(W, nbk * 16);
+  int split = 1;
+  while (split < 8 && (gr.tiles * split < 2 * (int64_t)c->num_cu || rbytes / split > 2.0 * 1024 * 1024) &&
+         nK / (2 * split) >= 8)
+    split *= 2;
+  gr.split = split;
+  gr.xcd = 1;
+  float* part = nullptr;
+  if (split > 1) {
+    const int rc = ensure_work(c, (size_t)split * (size_t)m * (size_t)W * sizeof(float));
+    if (rc) return rc;
+    part = (float*)c->work;
   }
-  SK_BF_CASE(2) SK_BF_CASE(4) SK_BF_CASE(8) SK_BF_CASE(16)
+  // XCD-major order: 8 / split XCDs per source slice, row tiles dealt over them
+  const int per = 8 / split;
+  const int64_t nblk = 8 * ((gr.tiles + per - 1) / per);
+  dim3 grid((unsigned)nblk);
+  {
+    ProfScope ps(c, x3 ? (TRANS ? "gauss_bf16x3_t" : "gauss_bf16x3") : (TRANS ? "gauss_bf16_t" : "gauss_bf16"), st);
+#define SK_BF_CASE(NB_)                                                                                       \
+  if (nbk == NB_) {                                                                                           \
+    if (x3)                                                                                                   \
+      gauss_bf16_kernel<NB_, true, TRANS><<<grid, 256, 0, st>>>(A, lda, m, n, g, n, W, S, ldS, scale, gr, part); \
+    else                                                                                                      \
+      gauss_bf16_kernel<NB_, false, TRANS><<<grid, 256, 0, st>>>(A, lda, m, n, g, n, W, S, ldS, scale, gr, part); \
+  }
+    SK_BF_CASE(2) SK_BF_CASE(4) SK_BF_CASE(8) SK_BF_CASE(16)
 #undef SK_BF_CASE
-  SK_HIP(hipGetLastError());
+    SK_HIP(hipGetLastError());
+  }
+  if (split > 1) {
+    ProfScope ps(c, "gauss_reduce", st);
+    split_reduce_any(SK_F32, part, split, m, W, S, ldS, (double)scale, st);
+    SK_HIP(hipGetLastError());
+  }
   return SK_OK;
 }
 
