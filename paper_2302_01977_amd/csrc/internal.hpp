@@ -166,6 +166,10 @@ int launch_sjlt_dma(Ctx* c, int dtype, int nw, int nj, int rpl, int kc, const vo
                     int64_t K, const SjltPass& pass, void* out, int64_t ldo, double scale, int split, void* part,
                     int gz, hipStream_t st);
 size_t dma_lds_bytes(int esz, int kc, int tl, int nblk, int kcap);
+int launch_sjlt_dma_t(Ctx* c, int dtype, int nw, int nj, int kc, const void* A, int64_t lda, int64_t L, int64_t K,
+                      const SjltPass& pass, void* out, int64_t ldo, double scale, int split, void* part,
+                      hipStream_t st);
+size_t dma_t_lds_bytes(int esz, int kc, int nblk, int kcap);
 
 int ensure_work(Ctx* c, size_t bytes);
 int sjlt_chunk_for(int w, int alpha, int lam);

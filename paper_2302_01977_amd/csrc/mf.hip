@@ -14,8 +14,8 @@
 //   dL/dh   =  sum_ij G_ij K_ij |x_i - x_j|^2 / h^3.
 // G_ij = sum_c sign(j,c) W(i, col(j,c)) / sqrt(alpha) reads the columns named by
 // the (uniform) hash of j from an LDS copy of W's rows i; G_ji reads row j of W
-// at the columns named by the hash of lane i, from a row-major copy of W (a
-// 1 KB row shared by the whole wave).  dL/dx terms are summed in FP32 over a
+// at the columns named by the hash of lane i, from an LDS slot of the wave into
+// which row j of a row-major copy of W (1 KB) is staged.  dL/dx terms are summed in FP32 over a
 // chunk of sources and in FP64 across chunks; dL/dh, a sum with heavy
 // cancellation, is accumulated in FP64 term by term.  Waves and workgroups are
 // combined in a fixed order, so the result is deterministic.
@@ -121,19 +121,28 @@ __global__ void __launch_bounds__(256) transpose_kernel(const float* __restrict_
   }
 }
 
-template <int DIM, int NWB, int KCB, int MAXA>
+// One workgroup owns 64 points i (lanes); its NWB waves split the sources j
+// into contiguous ranges.  G_ij reads the LDS copy of W's rows i (column named
+// by the uniform hash of j: conflict-free); G_ji reads row j of W, which each
+// wave stages in its own LDS slot (two rows at a time, the next two already in
+// flight in registers), at the columns named by the hash of lane i.
+template <int DIM, int NWB, int MAXA>
 __global__ void __launch_bounds__(NWB * 64)
     mf_bwd_kernel(const float* __restrict__ X, int64_t N, float c2, const float* __restrict__ W, int64_t ldw,
                   const float* __restrict__ Wrm, int Wt, MfBlocks mb, int alpha, float* __restrict__ dX,
                   float xscale, double* __restrict__ dh_part) {
-  __shared__ __attribute__((aligned(16))) float Wr[256 * 64];  // Wr[col * 64 + lane] = W(l0 + lane, col), col < Wt
-  __shared__ double red[NWB][DIM + 1][64];
+  constexpr int SRC = 2;    // sources staged per step and wave
+  constexpr int GRP = 32;   // sources summed in FP32 before the FP64 accumulators
+  extern __shared__ __attribute__((aligned(16))) float smem_f[];
+  float* const Wr = smem_f;                   // Wr[col * 64 + lane] = W(l0 + lane, col), col < Wt
+  float* const Wj = smem_f + (size_t)Wt * 64;  // per wave: SRC staged rows of Wt floats
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t l0 = (int64_t)blockIdx.x * 64;
   const int64_t i = l0 + lane;
   const bool lane_ok = i < N;
+  float* const myrows = Wj + (size_t)wave * SRC * Wt;
 
   for (int e = tid; e < Wt * 64; e += NWB * 64) {
     const int col = e >> 6, r = e & 63;
@@ -159,17 +168,38 @@ __global__ void __launch_bounds__(NWB * 64)
   }
   __syncthreads();
 
+  // this wave's sources [js, je); rows are Wt / 4 pieces of 16 bytes
+  const int64_t js = N * wave / NWB, je = N * (wave + 1) / NWB;
+  const int npc = Wt / 4;
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  f4v pf[SRC];
+  auto fetch = [&](int64_t j0) {
+#pragma unroll
+    for (int u = 0; u < SRC; ++u) {
+      const int64_t j = j0 + u;
+      pf[u] = (lane < npc && j < je) ? *(const f4v*)(Wrm + j * Wt + 4 * lane) : f4v{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+
   double ax[DIM], ah = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) ax[d] = 0.0;
-  for (int64_t j0 = (int64_t)wave * KCB; j0 < N; j0 += (int64_t)NWB * KCB) {
-    float px[DIM];
+  float px[DIM];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) px[d] = 0.f;
-    const int jn = (int)std::min<int64_t>(KCB, N - j0);
-#pragma unroll 2
-    for (int jj = 0; jj < jn; ++jj) {
-      const int64_t j = j0 + jj;
+  for (int d = 0; d < DIM; ++d) px[d] = 0.f;
+  int ng = 0;
+  if (js < je) fetch(js);
+  for (int64_t j0 = js; j0 < je; j0 += SRC) {
+    // stage this step's rows (the wave's earlier reads of its slot are done:
+    // LDS operations of one wave complete in order), then fetch the next step
+#pragma unroll
+    for (int u = 0; u < SRC; ++u)
+      if (lane < npc) *(f4v*)(myrows + u * Wt + 4 * lane) = pf[u];
+    if (j0 + SRC < je) fetch(j0 + SRC);
+#pragma unroll
+    for (int u = 0; u < SRC; ++u) {
+      const int64_t j = j0 + u;
+      if (j >= je) break;
       float df[DIM], r2 = 0.f;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
@@ -178,7 +208,7 @@ __global__ void __launch_bounds__(NWB * 64)
       }
       const float K = __builtin_amdgcn_exp2f(-r2 * c2);
       float gij = 0.f, gji = 0.f;
-      const float* __restrict__ wrow = Wrm + j * Wt;
+      const float* __restrict__ wrow = myrows + u * Wt;
 #pragma unroll
       for (int q = 0; q < MAXA; ++q) {
         if (q < na) {
@@ -194,12 +224,24 @@ __global__ void __launch_bounds__(NWB * 64)
       for (int d = 0; d < DIM; ++d) px[d] = fmaf(M, df[d], px[d]);
       ah += (double)(gij * K * r2);  // dL/dh cancels heavily: accumulate its terms in FP64
     }
+    ng += SRC;
+    if (ng >= GRP) {
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) ax[d] += (double)px[d];
+      for (int d = 0; d < DIM; ++d) {
+        ax[d] += (double)px[d];
+        px[d] = 0.f;
+      }
+      ng = 0;
+    }
   }
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) red[wave][d][lane] = ax[d];
-  red[wave][DIM][lane] = lane_ok ? ah : 0.0;
+  for (int d = 0; d < DIM; ++d) ax[d] += (double)px[d];
+  // combine the waves in a fixed order (the LDS rows of W are no longer read)
+  __syncthreads();
+  double* const red = (double*)smem_f;  // [NWB][DIM + 1][64]
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) red[(wave * (DIM + 1) + d) * 64 + lane] = ax[d];
+  red[(wave * (DIM + 1) + DIM) * 64 + lane] = lane_ok ? ah : 0.0;
   __syncthreads();
   if (wave == 0) {
     double sx[DIM], sh = 0.0;
@@ -207,19 +249,19 @@ __global__ void __launch_bounds__(NWB * 64)
     for (int d = 0; d < DIM; ++d) sx[d] = 0.0;
     for (int q = 0; q < NWB; ++q) {
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) sx[d] += red[q][d][lane];
-      sh += red[q][DIM][lane];
+      for (int d = 0; d < DIM; ++d) sx[d] += red[(q * (DIM + 1) + d) * 64 + lane];
+      sh += red[(q * (DIM + 1) + DIM) * 64 + lane];
     }
     if (lane_ok) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) dX[i * DIM + d] = (float)(sx[d] * (double)xscale);
     }
-    red[0][DIM][lane] = sh;
+    red[DIM * 64 + lane] = sh;  // slot of wave 0, item DIM: read back below by thread 0 only
   }
   __syncthreads();
   if (tid == 0) {
     double t = 0.0;
-    for (int l = 0; l < 64; ++l) t += red[0][DIM][l];
+    for (int l = 0; l < 64; ++l) t += red[DIM * 64 + l];
     dh_part[blockIdx.x] = t;
   }
 }
@@ -350,16 +392,21 @@ int launch_mf_backward(Handle* h, const sk_input* in, int b0, int b1, const floa
   const float c2 = (float)(LOG2E / (2.0 * hh * hh));
   const double ga = 1.0 / sqrt((double)h->alpha);
   const float xscale = (float)(-ga / (hh * hh));
-  constexpr int NWB = 4, KCB = 32;
+  constexpr int NWB = 8;
+  // W rows i + two staged rows j per wave; the end-of-kernel reduction reuses it
+  const size_t shmem = std::max((size_t)Wt * 64 * 4 + (size_t)NWB * 2 * Wt * 4, (size_t)NWB * 5 * 64 * 8);
   {
     ProfScope ps(h->ctx, "mf_bwd", st);
     const dim3 grid((unsigned)nwg);
-    switch (in->dim) {
-      case 1: mf_bwd_kernel<1, NWB, KCB, 16><<<grid, NWB * 64, 0, st>>>(in->X, N, c2, Wd, ldw, Wrm, Wt, mb, h->alpha, dX, xscale, dh_part); break;
-      case 2: mf_bwd_kernel<2, NWB, KCB, 16><<<grid, NWB * 64, 0, st>>>(in->X, N, c2, Wd, ldw, Wrm, Wt, mb, h->alpha, dX, xscale, dh_part); break;
-      case 3: mf_bwd_kernel<3, NWB, KCB, 16><<<grid, NWB * 64, 0, st>>>(in->X, N, c2, Wd, ldw, Wrm, Wt, mb, h->alpha, dX, xscale, dh_part); break;
-      default: mf_bwd_kernel<4, NWB, KCB, 16><<<grid, NWB * 64, 0, st>>>(in->X, N, c2, Wd, ldw, Wrm, Wt, mb, h->alpha, dX, xscale, dh_part); break;
+    auto kern = in->dim == 1 ? mf_bwd_kernel<1, NWB, 16>
+                : in->dim == 2 ? mf_bwd_kernel<2, NWB, 16>
+                : in->dim == 3 ? mf_bwd_kernel<3, NWB, 16> : mf_bwd_kernel<4, NWB, 16>;
+    static bool attr_set[4] = {false, false, false, false};
+    if (!attr_set[in->dim - 1]) {
+      SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+      attr_set[in->dim - 1] = true;
     }
+    kern<<<grid, NWB * 64, shmem, st>>>(in->X, N, c2, Wd, ldw, Wrm, Wt, mb, h->alpha, dX, xscale, dh_part);
     SK_HIP(hipGetLastError());
   }
   dh_reduce_kernel<<<1, 64, 0, st>>>(dh_part, nwg, ga / (hh * hh * hh), dh);

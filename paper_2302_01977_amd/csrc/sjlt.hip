@@ -169,15 +169,32 @@ static DmaShape choose_dma(int dtype, int kc, int W, int g, int nblk, int kcap) 
 
 // Chunk sizes of a dense operator of width d.  S: about two entries per bucket
 // when the direct-to-LDS kernel has a shape for it (it double-buffers the tile,
-// so shorter chunks keep it in LDS), else about four.  S' (register-staged
-// kernel): about four in FP64, two in FP32.  A direct-to-LDS S' kernel was
-// measured slower on MI355X: a lane's sources run down one column of A, and the
-// double-buffered tile limits those runs to 1 KB.  kct = 0 when S' shares the
-// S tables.
+// so shorter chunks keep it in LDS), else about four.  S': the 1 KB column
+// chunks of the direct-to-LDS S' kernel when it applies, else (register-staged
+// kernel) about four entries per bucket in FP64, two in FP32.  kct = 0 when S'
+// shares the S tables.
+// Shape of the direct-to-LDS S' kernel: one 1 KB chunk per column (KC = 256
+// sources in FP32), NJ columns per wave; nw = 0 when it does not apply.  The
+// FP64 instances (KC = 128) were measured no faster than the register-staged
+// kernel on MI355X (w = 256) or slower (w = 64, 0.70 against 0.52 ms at
+// n = 16384), so FP64 keeps the register-staged S'.
+static DmaShape choose_dma_t(int dtype, int kc, int W, int g, int nblk, int kcap) {
+  const int esz = dtype == SK_F64 ? 8 : 4;
+  if (dtype == SK_F64 || kc * esz != 1024) return DmaShape{0, 0, 0};
+  const int nj = W >= 256 ? 16 : W >= 128 ? 8 : 4;
+  if (g % nj != 0 || W / nj > MAX_PASS_GROUPS) return DmaShape{0, 0, 0};
+  if ((int64_t)nblk * kcap > 16 * 64 * 8) return DmaShape{0, 0, 0};
+  if (dma_t_lds_bytes(esz, kc, nblk, kcap) > 160 * 1024) return DmaShape{0, 0, 0};
+  return DmaShape{16, nj, 1};
+}
+
 void sjlt_pick_chunks(int dtype, int d, int alpha, bool want_t, int* kc, int* kct) {
   const int k2 = sjlt_chunk_for(d, alpha, 2);
   *kc = choose_dma(dtype, k2, d, d, 1, sjlt_kcap(k2, alpha, d)).nw ? k2 : sjlt_chunk_for(d, alpha, 4);
-  const int kt = sjlt_chunk_for(d, alpha, dtype == SK_F64 ? 4 : 2);
+  const int kd = dtype == SK_F64 ? 128 : 256;
+  const int kt = choose_dma_t(dtype, kd, d, d, 1, sjlt_kcap(kd, alpha, d)).nw
+                     ? kd
+                     : sjlt_chunk_for(d, alpha, dtype == SK_F64 ? 4 : 2);
   *kct = want_t && kt != *kc ? kt : 0;
 }
 
@@ -296,9 +313,12 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
   {
     // (direct-to-LDS 16-byte loads: A and its columns 16-byte aligned)
     const bool al16 = (uintptr_t)in->A % 16 == 0 && (in->lda * (int64_t)esz) % 16 == 0;
-    DmaShape ds = trans || !al16 ? DmaShape{0, 0, 0} : choose_dma(h->dtype, kc, W, g, nblk, pass.kcap);
+    DmaShape ds = !al16 ? DmaShape{0, 0, 0}
+                  : trans ? choose_dma_t(h->dtype, kc, W, g, nblk, pass.kcap)
+                          : choose_dma(h->dtype, kc, W, g, nblk, pass.kcap);
     if (ds.nw) {
-      const size_t dbytes = dma_lds_bytes((int)esz, kc, 64 * ds.rpl, nblk, pass.kcap);
+      const size_t dbytes = trans ? dma_t_lds_bytes((int)esz, kc, nblk, pass.kcap)
+                                  : dma_lds_bytes((int)esz, kc, 64 * ds.rpl, nblk, pass.kcap);
       const int64_t dtiles = (L + 64 * ds.rpl - 1) / (64 * ds.rpl);
       const int64_t dtarget = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)dbytes) * c->num_cu;
       int dsplit = 1;
@@ -319,8 +339,10 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
         if ((rc = ensure_work(c, (size_t)dsplit * (size_t)L * (size_t)W * esz))) return rc;
         dpart = c->work;
       }
-      rc = launch_sjlt_dma(c, h->dtype, ds.nw, ds.nj, ds.rpl, kc, in->A, in->lda, L, K, dp, out, ldo, scale, dsplit,
-                           dpart, 1, st);
+      rc = trans ? launch_sjlt_dma_t(c, h->dtype, ds.nw, ds.nj, kc, in->A, in->lda, L, K, dp, out, ldo, scale,
+                                     dsplit, dpart, st)
+                 : launch_sjlt_dma(c, h->dtype, ds.nw, ds.nj, ds.rpl, kc, in->A, in->lda, L, K, dp, out, ldo, scale,
+                                   dsplit, dpart, 1, st);
       if (rc != 1) {
         if (rc) return rc;
         if (dsplit > 1) {
