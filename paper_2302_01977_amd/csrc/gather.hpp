@@ -72,7 +72,9 @@ namespace sk {
 // straight-line code (slots past the bucket's end read the zero row at zaddr),
 // four independent reads at a time; the rest of a longer bucket follows in
 // pairs (and a last single entry).
-template <typename T, int NJ, int RPL, typename VT>
+// With PACK, E holds one word per entry instead: the address with the sign in
+// bit 31.
+template <typename T, int NJ, int RPL, typename VT, bool PACK = false>
 __device__ __forceinline__ void gather_chunk_lds(const uint32_t* E, int ebase, uint32_t bnd, uint32_t bndN,
                                                  uint32_t lane_part, uint32_t zaddr, int ms,
                                                  T (&acc)[NJ][RPL]) {
@@ -80,7 +82,14 @@ __device__ __forceinline__ void gather_chunk_lds(const uint32_t* E, int ebase, u
   typedef __attribute__((address_space(3))) const VT* lds_vt;
   constexpr int EW = sizeof(T) == 8 ? 4 : 2;
   auto entry = [&](int e, uint32_t& addr, T& sgn) {
-    if constexpr (EW == 4) {
+    if constexpr (PACK) {
+      const uint32_t w = E[e];
+      addr = (w & 0x7fffffffu) ^ lane_part;
+      if constexpr (sizeof(T) == 8)
+        sgn = __builtin_bit_cast(T, (uint64_t)((w & 0x80000000u) | 0x3ff00000u) << 32);
+      else
+        sgn = __builtin_bit_cast(T, (w & 0x80000000u) | 0x3f800000u);
+    } else if constexpr (EW == 4) {
       const u4 a = *(const u4*)&E[e * 4];
       addr = a[0] ^ lane_part;
       sgn = __builtin_bit_cast(T, ((uint64_t)a[3] << 32) | a[2]);
@@ -200,6 +209,101 @@ __device__ __forceinline__ void gather_chunk_lds_ms(const uint32_t* E, int ebase
       const VT x0 = *(lds_vt)(uintptr_t)a0;
 #pragma unroll
       for (int r = 0; r < RPL; ++r) acc[jj][r] = fma(((const T*)&x0)[r], s0, acc[jj][r]);
+    }
+  }
+}
+
+
+// Gather with one 32-bit word per staged entry: the LDS address of the source
+// row with the sign in bit 31 (RPL = 1).  Two adjacent entries come in one
+// ds_read2_b32; the sign is applied by flipping the sign bit of the value.
+template <typename T>
+__device__ __forceinline__ T flip_sign(T v, uint32_t w) {
+  if constexpr (sizeof(T) == 8) {
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    u ^= (uint64_t)(w & 0x80000000u) << 32;
+    return __builtin_bit_cast(T, u);
+  } else {
+    return __builtin_bit_cast(T, __builtin_bit_cast(uint32_t, v) ^ (w & 0x80000000u));
+  }
+}
+
+template <typename T, int NJ, int MS>
+__device__ __forceinline__ void gather_chunk_e32(const uint32_t* E, int ebase, uint32_t bnd, uint32_t bndN,
+                                                 uint32_t lane_part, uint32_t zaddr, T (&acc)[NJ][1]) {
+  typedef __attribute__((address_space(3))) const T* lds_t;
+  static_assert(MS % 2 == 0, "slots come in pairs");
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) {
+    const int e0 = (int)__builtin_amdgcn_readlane(bnd, jj) - ebase;
+    const int e1 = (jj + 1 < NJ ? (int)__builtin_amdgcn_readlane(bnd, jj + 1)
+                                : (int)__builtin_amdgcn_readfirstlane(bndN)) - ebase;
+    uint32_t w[MS];
+#pragma unroll
+    for (int q = 0; q < MS; ++q) w[q] = E[e0 + q];
+    T x[MS];
+#pragma unroll
+    for (int q = 0; q < MS; ++q) {
+      const uint32_t ad = e0 + q < e1 ? ((w[q] & 0x7fffffffu) ^ lane_part) : zaddr;
+      x[q] = *(lds_t)(uintptr_t)ad;
+    }
+    T a = acc[jj][0];
+#pragma unroll
+    for (int q = 0; q < MS; ++q) a += flip_sign(x[q], w[q]);
+    int e = e0 + MS;
+    for (; e + 1 < e1; e += 2) {
+      const uint32_t w0 = E[e], w1 = E[e + 1];
+      const T x0 = *(lds_t)(uintptr_t)((w0 & 0x7fffffffu) ^ lane_part);
+      const T x1 = *(lds_t)(uintptr_t)((w1 & 0x7fffffffu) ^ lane_part);
+      a += flip_sign(x0, w0);  // one add at a time: the order of the FMA gathers
+      a += flip_sign(x1, w1);
+    }
+    if (e < e1) {  // odd overflow
+      const uint32_t w0 = E[e];
+      a += flip_sign(*(lds_t)(uintptr_t)((w0 & 0x7fffffffu) ^ lane_part), w0);
+    }
+    acc[jj][0] = a;
+  }
+}
+
+
+// The same with RPL rows per lane (VT holds RPL consecutive elements).
+template <typename T, int NJ, int RPL, typename VT, int MS>
+__device__ __forceinline__ void gather_chunk_e32_rpl(const uint32_t* E, int ebase, uint32_t bnd, uint32_t bndN,
+                                                     uint32_t lane_part, uint32_t zaddr, T (&acc)[NJ][RPL]) {
+  typedef __attribute__((address_space(3))) const VT* lds_vt;
+  auto add = [&](T(&a)[RPL], const VT& x, uint32_t w) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) a[r] += flip_sign(((const T*)&x)[r], w);
+  };
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) {
+    const int e0 = (int)__builtin_amdgcn_readlane(bnd, jj) - ebase;
+    const int e1 = (jj + 1 < NJ ? (int)__builtin_amdgcn_readlane(bnd, jj + 1)
+                                : (int)__builtin_amdgcn_readfirstlane(bndN)) - ebase;
+    uint32_t w[MS];
+#pragma unroll
+    for (int q = 0; q < MS; ++q) w[q] = E[e0 + q];
+    VT x[MS];
+#pragma unroll
+    for (int q = 0; q < MS; ++q) {
+      const uint32_t ad = e0 + q < e1 ? ((w[q] & 0x7fffffffu) ^ lane_part) : zaddr;
+      x[q] = *(lds_vt)(uintptr_t)ad;
+    }
+#pragma unroll
+    for (int q = 0; q < MS; ++q) add(acc[jj], x[q], w[q]);
+    int e = e0 + MS;
+    for (; e + 1 < e1; e += 2) {
+      const uint32_t w0 = E[e], w1 = E[e + 1];
+      const VT x0 = *(lds_vt)(uintptr_t)((w0 & 0x7fffffffu) ^ lane_part);
+      const VT x1 = *(lds_vt)(uintptr_t)((w1 & 0x7fffffffu) ^ lane_part);
+      add(acc[jj], x0, w0);
+      add(acc[jj], x1, w1);
+    }
+    if (e < e1) {
+      const uint32_t w0 = E[e];
+      const VT x0 = *(lds_vt)(uintptr_t)((w0 & 0x7fffffffu) ^ lane_part);
+      add(acc[jj], x0, w0);
     }
   }
 }

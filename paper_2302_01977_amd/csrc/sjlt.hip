@@ -183,6 +183,9 @@ static DmaShape choose_dma_t(int dtype, int kc, int W, int g, int nblk, int kcap
   if (dtype == SK_F64 || kc * esz != 1024) return DmaShape{0, 0, 0};
   const int nj = W >= 256 ? 16 : W >= 128 ? 8 : 4;
   if (g % nj != 0 || W / nj > MAX_PASS_GROUPS) return DmaShape{0, 0, 0};
+  // long buckets (more than about eight entries per chunk) gather faster in the
+  // register-staged kernel (measured: w = 64, alpha = 8)
+  if ((int64_t)nblk * kcap > 8 * (int64_t)W) return DmaShape{0, 0, 0};
   if ((int64_t)nblk * kcap > 16 * 64 * 8) return DmaShape{0, 0, 0};
   if (dma_t_lds_bytes(esz, kc, nblk, kcap) > 160 * 1024) return DmaShape{0, 0, 0};
   return DmaShape{16, nj, 1};

@@ -20,7 +20,6 @@ __global__ void __launch_bounds__(NW * 64)
   constexpr int TL = 64 * RPL;
   constexpr int NTHR = NW * 64;
   constexpr int NSLOT = KCK + 1;
-  constexpr int EW = SZ == 8 ? 4 : 2;
   constexpr int TBYTES = NSLOT * TL * SZ;        // one tile buffer, zero slot included
   constexpr int UNITS = KCK * TL * SZ / 1024;    // 1 KB wave loads per chunk
   static_assert((KCK * TL * SZ) % 1024 == 0, "a chunk is a whole number of KB");
@@ -30,6 +29,10 @@ __global__ void __launch_bounds__(NW * 64)
   // the same block as an LDS-address-space pointer (direct-to-LDS destinations)
   __attribute__((address_space(3))) char* const smem3 = (__attribute__((address_space(3))) char*)smem;
   const uint32_t lds0 = (uint32_t)(uintptr_t)smem3;
+  // entries in LDS: FP64 one word (address, sign in bit 31); FP32 two words
+  // (address, +-1.0f), which measured faster for the FP32 gather
+  constexpr bool PACK = SZ == 8;
+  constexpr int EW = PACK ? 1 : 2;
   const int ebytes = (pass.nblk * pass.kcap + 8) * EW * 4;  // one entry buffer (+8: masked slot reads)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -105,18 +108,20 @@ __global__ void __launch_bounds__(NW * 64)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (!eptr[h]) continue;
-      uint32_t ad[4], sg[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t src = ebuf[h][q] >> 1;
-        ad[q] = base + src * (uint32_t)(TL * SZ);
-        sg[q] = ((ebuf[h][q] & 1u) << 31) | (SZ == 8 ? 0x3ff00000u : 0x3f800000u);
-      }
       const int qb = (tid + h * NTHR) * 4;
-      if constexpr (EW == 4) {
+      if constexpr (PACK) {
+        u32x4 wd;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) *(u32x4*)&ents[(qb + q) * 4] = u32x4{ad[q], 0u, 0u, sg[q]};
+        for (int q = 0; q < 4; ++q)
+          wd[q] = (base + (ebuf[h][q] >> 1) * (uint32_t)(TL * SZ)) | (ebuf[h][q] << 31);
+        *(u32x4*)&ents[qb] = wd;
       } else {
+        uint32_t ad[4], sg[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ad[q] = base + (ebuf[h][q] >> 1) * (uint32_t)(TL * SZ);
+          sg[q] = ((ebuf[h][q] & 1u) << 31) | 0x3f800000u;
+        }
         *(u32x4*)&ents[qb * 2] = u32x4{ad[0], sg[0], ad[1], sg[1]};
         *(u32x4*)&ents[qb * 2 + 4] = u32x4{ad[2], sg[2], ad[3], sg[3]};
       }
@@ -150,9 +155,17 @@ __global__ void __launch_bounds__(NW * 64)
       load_meta(t + 1);
       load_tile(t + 1, b ^ 1);
     }
-    if (active)
-      gather_chunk_lds_ms<T, NJ, RPL, VT, MS>(ents_of(b), (t - blk) * pass.kcap, bnd, bndN, lane_part,
-                                              b ? zaddr1 : zaddr0, acc);
+    if (active) {
+      if constexpr (!PACK)
+        gather_chunk_lds_ms<T, NJ, RPL, VT, MS>(ents_of(b), (t - blk) * pass.kcap, bnd, bndN, lane_part,
+                                                b ? zaddr1 : zaddr0, acc);
+      else if constexpr (RPL == 1)
+        gather_chunk_e32<T, NJ, MS>(ents_of(b), (t - blk) * pass.kcap, bnd, bndN, lane_part, b ? zaddr1 : zaddr0,
+                                    acc);
+      else
+        gather_chunk_e32_rpl<T, NJ, RPL, VT, MS>(ents_of(b), (t - blk) * pass.kcap, bnd, bndN, lane_part,
+                                                 b ? zaddr1 : zaddr0, acc);
+    }
   }
 
   if (!active) return;
@@ -184,7 +197,6 @@ __global__ void __launch_bounds__(NW * 64)
   constexpr int VECN = 16 / SZ;
   constexpr int TL = 64;
   constexpr int NTHR = NW * 64;
-  constexpr int EW = SZ == 8 ? 4 : 2;
   constexpr int CSTR = (KCK + 8) * SZ;   // bytes between the staged columns
   constexpr int TBYTES = TL * CSTR;      // one tile buffer (also holds rows 0..KC of the moved tile)
   constexpr int RB = TL * SZ;            // bytes of one moved row
@@ -197,7 +209,7 @@ __global__ void __launch_bounds__(NW * 64)
   extern __shared__ __attribute__((aligned(16))) char smem[];
   __attribute__((address_space(3))) char* const smem3 = (__attribute__((address_space(3))) char*)smem;
   const uint32_t lds0 = (uint32_t)(uintptr_t)smem3;
-  const int ebytes = (pass.nblk * pass.kcap + 8) * EW * 4;
+  const int ebytes = (pass.nblk * pass.kcap + 8) * 4;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -255,28 +267,20 @@ __global__ void __launch_bounds__(NW * 64)
       }
     }
   };
-  // entries as (address of the source's moved row, +-1.0)
+  // entries as one word: address of the source's moved row, sign in bit 31
   auto store_meta = [&](int b) {
     uint32_t* ents = ents_of(b);
     const uint32_t base = tile_base(b);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (!eptr[h]) continue;
-      uint32_t ad[4], sg[4];
+      u32x4 wd;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint32_t src = ebuf[h][q] >> 1;
-        ad[q] = base + src * (uint32_t)RB + ((src & 7u) * 8u) * (uint32_t)SZ;
-        sg[q] = ((ebuf[h][q] & 1u) << 31) | (SZ == 8 ? 0x3ff00000u : 0x3f800000u);
+        wd[q] = (base + src * (uint32_t)RB + ((src & 7u) * 8u) * (uint32_t)SZ) | (ebuf[h][q] << 31);
       }
-      const int qb = (tid + h * NTHR) * 4;
-      if constexpr (EW == 4) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) *(u32x4*)&ents[(qb + q) * 4] = u32x4{ad[q], 0u, 0u, sg[q]};
-      } else {
-        *(u32x4*)&ents[qb * 2] = u32x4{ad[0], sg[0], ad[1], sg[1]};
-        *(u32x4*)&ents[qb * 2 + 4] = u32x4{ad[2], sg[2], ad[3], sg[3]};
-      }
+      *(u32x4*)&ents[(tid + h * NTHR) * 4] = wd;
     }
     bnd = bnd_nx;
     bndN = bndN_nx;
@@ -317,8 +321,8 @@ __global__ void __launch_bounds__(NW * 64)
     if (wave == NW - 1) *(T*)(tb + KCK * RB + lane * SZ) = T(0);  // row KC: masked slots and null entries
     __syncthreads();
     if (active)
-      gather_chunk_lds_ms<T, NJ, 1, VT, MS>(ents_of(b), (t - blk) * pass.kcap, bnd, bndN, lane_part,
-                                            (tile_base(b) + (uint32_t)(KCK * RB)) ^ lane_part, acc);
+      gather_chunk_e32<T, NJ, MS>(ents_of(b), (t - blk) * pass.kcap, bnd, bndN, lane_part,
+                                  (tile_base(b) + (uint32_t)(KCK * RB)) ^ lane_part, acc);
   }
 
   if (!active) return;
@@ -333,8 +337,7 @@ __global__ void __launch_bounds__(NW * 64)
 }
 
 size_t dma_t_lds_bytes(int esz, int kc, int nblk, int kcap) {
-  const size_t ew = esz == 8 ? 16 : 8;
-  return 2 * (size_t)64 * (kc + 8) * esz + 2 * ((size_t)nblk * kcap + 8) * ew;
+  return 2 * (size_t)64 * (kc + 8) * esz + 2 * ((size_t)nblk * kcap + 8) * 4;
 }
 
 template <typename T, int NW, int NJ, int KCK>
@@ -372,8 +375,7 @@ int launch_sjlt_dma_t(Ctx* c, int dtype, int nw, int nj, int kc, const void* A, 
 }
 
 size_t dma_lds_bytes(int esz, int kc, int tl, int nblk, int kcap) {
-  const size_t ew = esz == 8 ? 16 : 8;
-  return 2 * (size_t)(kc + 1) * tl * esz + 2 * ((size_t)nblk * kcap + 8) * ew;
+  return 2 * (size_t)(kc + 1) * tl * esz + 2 * ((size_t)nblk * kcap + 8) * (esz == 8 ? 4 : 8);
 }
 
 template <typename T, int NW, int NJ, int RPL, int KCK>

@@ -91,10 +91,11 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
   typedef typename VecT<T, RPL>::type VT;
 
   // Dynamic LDS: the staged tile, whose extra source slot KCK holds zeros (the
-  // source of null entries), then (LDSE) the chunk's bucket entries, EW words
-  // each: the entry's LDS address in the tile and its sign as +-1.0.
+  // source of null entries), then (LDSE) the chunk's bucket entries: FP64 one
+  // word (the entry's LDS address in the tile, its sign in bit 31), FP32 two
+  // words (address, sign as +-1.0f).
   constexpr int NSLOT = KCK + 1;
-  constexpr int EW = SZ == 8 ? 4 : 2;
+  constexpr bool PACK = SZ == 8;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   T* tile = (T*)smem;
   uint32_t* ents = (uint32_t*)(smem + NSLOT * TL * SZ);
@@ -184,13 +185,12 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
         for (int q = 0; q < 4; ++q) {
           const uint32_t src = ebuf[h][q] >> 1;
           ad[q] = (tile_lds + src * (uint32_t)(TL * SZ)) | (TRANS ? ((src / VECN) & 15u) * 16u : 0u);
-          // the sign as +-1.0 (high word of the double for FP64)
-          sg[q] = ((ebuf[h][q] & 1u) << 31) | (SZ == 8 ? 0x3ff00000u : 0x3f800000u);
+          sg[q] = ((ebuf[h][q] & 1u) << 31) | 0x3f800000u;
         }
         const int qb = q0[h];
-        if constexpr (EW == 4) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) *(u32x4*)&ents[(qb + q) * 4] = u32x4{ad[q], 0u, 0u, sg[q]};
+        if constexpr (PACK) {
+          *(u32x4*)&ents[qb] = u32x4{ad[0] | (ebuf[h][0] << 31), ad[1] | (ebuf[h][1] << 31),
+                                     ad[2] | (ebuf[h][2] << 31), ad[3] | (ebuf[h][3] << 31)};
         } else {
           *(u32x4*)&ents[qb * 2] = u32x4{ad[0], sg[0], ad[1], sg[1]};
           *(u32x4*)&ents[qb * 2 + 4] = u32x4{ad[2], sg[2], ad[3], sg[3]};
@@ -258,7 +258,7 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
     if (t + 1 < t1) load_chunk(t + 1);  // in flight during the gather below
     if (active) {
       if constexpr (LDSE)
-        gather_chunk_lds<T, NJ, RPL, VT>(ents, (t - blk) * kcap, bnd, bndN, lane_part, zaddr, ms, acc);
+        gather_chunk_lds<T, NJ, RPL, VT, PACK>(ents, (t - blk) * kcap, bnd, bndN, lane_part, zaddr, ms, acc);
       else
         gather_chunk<T, NJ, RPL, VT>(ptr + (int64_t)t * prow, ent, LD, acc);
     }
@@ -276,7 +276,7 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
 
 // dynamic LDS of one workgroup: the tile with its zero slot, then the entries
 inline size_t gather_lds_bytes(int esz, int kc, int tl, bool ldse, int nblk, int kcap) {
-  const size_t ew = esz == 8 ? 16 : 8;
+  const size_t ew = esz == 8 ? 4 : 8;
   // (+8 entries: the straight-line slots of the last bucket may read up to 7 past it)
   return (size_t)(kc + 1) * tl * esz + (ldse ? ((size_t)nblk * kcap + 8) * ew : 0);
 }
