@@ -26,11 +26,17 @@
 
 namespace sk {
 
-template <int NW, int NJ, int KCK, int DIM>
+template <int NW, int NJ, int KCK, int DIM, bool LDSE>
 __global__ void __launch_bounds__(NW * 64)
     mf_sjlt_kernel(const float* __restrict__ X, int64_t N, float c2, float shift, SjltPass pass,
                    float* __restrict__ out, int64_t ldo, float scale, int split, float* __restrict__ part) {
-  __shared__ __attribute__((aligned(16))) float tile[(KCK + 1) * 64];  // slot KCK: zeros for null entries
+  // dynamic LDS: the tile (slot KCK: zeros for null entries), then (LDSE) the
+  // chunk's bucket entries as (LDS address of the source row, +-1.0f)
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  float* const tile = (float*)smem;
+  uint32_t* const ents = (uint32_t*)(smem + (KCK + 1) * 64 * 4);
+  constexpr int NTHR = NW * 64;
+  const uint32_t tile_lds = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char*)smem;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -53,25 +59,91 @@ __global__ void __launch_bounds__(NW * 64)
   for (int d = 0; d < DIM; ++d) xi[d] = i < N ? X[i * DIM + d] : 0.f;
   if (tid < 64) tile[KCK * 64 + tid] = 0.f;
 
+  // LDSE staging (as in the stored-A kernels): thread tid moves entries
+  // [4 tid, 4 tid + 4) and [4 (tid + NTHR), ...) of the pass's chunk regions,
+  // one chunk ahead; lane jj of bnd holds the start of the wave's column jj
+  const uint32_t* eptr[2] = {nullptr, nullptr};
+  if constexpr (LDSE) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q0 = (tid + h * NTHR) * 4;
+      const int eb = __builtin_amdgcn_readfirstlane(q0 / pass.kcap);
+      if (eb < pass.nblk) eptr[h] = (const uint32_t*)pass.ent[eb] + (q0 - eb * pass.kcap);
+    }
+  }
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  u4 ebuf[2] = {u4{0u, 0u, 0u, 0u}, u4{0u, 0u, 0u, 0u}};
+  uint32_t bnd = 0, bndN = 0, bnd_nx = 0, bndN_nx = 0;
+  auto load_meta = [&](int t) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (eptr[h]) ebuf[h] = *(const u4*)(eptr[h] + (int64_t)t * pass.kcap);
+    if (active) {
+      const int32_t* pb = ptr + (int64_t)t * prow;
+      bnd_nx = lane < NJ ? (uint32_t)pb[lane] : 0u;
+      bndN_nx = (uint32_t)pb[NJ];
+    }
+  };
+  auto store_meta = [&]() {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!eptr[h]) continue;
+      uint32_t ad[4], sg[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ad[q] = tile_lds + (ebuf[h][q] >> 1) * 256u;
+        sg[q] = ((ebuf[h][q] & 1u) << 31) | 0x3f800000u;
+      }
+      const int qb = (tid + h * NTHR) * 4;
+      *(u4*)&ents[qb * 2] = u4{ad[0], sg[0], ad[1], sg[1]};
+      *(u4*)&ents[qb * 2 + 4] = u4{ad[2], sg[2], ad[3], sg[3]};
+    }
+    bnd = bnd_nx;
+    bndN = bndN_nx;
+  };
+
   float acc[NJ][1];
 #pragma unroll
   for (int jj = 0; jj < NJ; ++jj) acc[jj][0] = 0.f;
   const uint32_t lane_off = (uint32_t)lane * 4u;
+  const uint32_t zaddr = (tile_lds + (uint32_t)(KCK * 256)) ^ lane_off;
   const char* tbase = (const char*)tile;
   auto LD = [&](int v) -> float { return *(const float*)(tbase + ((uint32_t)v >> 1) * 256u + lane_off); };
 
+  // the wave's sources of a chunk are src = wave + NW r (r < SPW); lane r holds
+  // the coordinates of source r, loaded one chunk ahead and broadcast with
+  // readlane (no scalar-memory round trip per source)
+  constexpr int SPW = KCK / NW;
+  static_assert(SPW <= 64 && KCK % NW == 0, "one source per lane");
+  float xs[DIM];
+  auto load_xs = [&](int t) {
+    const int64_t k = (int64_t)t * KCK + wave + NW * lane;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xs[d] = (lane < SPW && k < N) ? X[k * DIM + d] : 0.f;
+  };
+
+  if (t0 < t1) {
+    if (LDSE) load_meta(t0);
+    load_xs(t0);
+  }
   for (int t = t0; t < t1; ++t) {
     const int64_t k0 = (int64_t)t * KCK;
     __syncthreads();  // previous chunk consumed
+    if constexpr (LDSE) store_meta();
+    float xc[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xc[d] = xs[d];
+    if (t + 1 < t1) load_xs(t + 1);
 #pragma unroll 4
-    for (int src = wave; src < KCK; src += NW) {
+    for (int r = 0; r < SPW; ++r) {
+      const int src = wave + NW * r;
       const int64_t k = k0 + src;
       float v = 0.f;
       if (k < N) {
         float d2 = 0.f;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-          const float df = xi[d] - X[k * DIM + d];
+          const float df = xi[d] - __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, xc[d]), r));
           d2 = fmaf(df, df, d2);
         }
         v = __builtin_amdgcn_exp2f(-d2 * c2);
@@ -79,8 +151,15 @@ __global__ void __launch_bounds__(NW * 64)
       }
       tile[src * 64 + lane] = v;
     }
+    if (LDSE && t + 1 < t1) load_meta(t + 1);  // in flight during the gather
     __syncthreads();
-    if (active) gather_chunk<float, NJ, 1, float>(ptr + (int64_t)t * prow, ent, LD, acc);
+    if (active) {
+      if constexpr (LDSE)
+        gather_chunk_lds<float, NJ, 1, float>(ents, (t - blk) * pass.kcap, bnd, bndN, lane_off, zaddr, pass.ms,
+                                              acc);
+      else
+        gather_chunk<float, NJ, 1, float>(ptr + (int64_t)t * prow, ent, LD, acc);
+    }
   }
   if (!active || i >= N) return;
   const int64_t jc = (int64_t)g * NJ;
@@ -188,8 +267,25 @@ __global__ void __launch_bounds__(NWB * 64)
 #pragma unroll
   for (int d = 0; d < DIM; ++d) px[d] = 0.f;
   int ng = 0;
+  // coordinates and hash codes of the sources, 64 at a time: lane r holds those
+  // of source jg + r, broadcast with readlane (no scalar-memory round trip per source)
+  float xg[DIM];
+  uint32_t cg[MAXA];
+  auto load_group = [&](int64_t jg) {
+    const int64_t j = jg + lane;
+    const bool ok = j < je;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xg[d] = ok ? X[j * DIM + d] : 0.f;
+#pragma unroll
+    for (int q = 0; q < MAXA; ++q) {
+      cg[q] = 0u;
+      if (q < na && ok) cg[q] = mb.codes[q / alpha][j * alpha + q % alpha];
+    }
+  };
   if (js < je) fetch(js);
   for (int64_t j0 = js; j0 < je; j0 += SRC) {
+    const int rl = (int)((j0 - js) & 63);  // lane of source j0 in the group registers
+    if (rl == 0) load_group(j0);
     // stage this step's rows (the wave's earlier reads of its slot are done:
     // LDS operations of one wave complete in order), then fetch the next step
 #pragma unroll
@@ -203,7 +299,7 @@ __global__ void __launch_bounds__(NWB * 64)
       float df[DIM], r2 = 0.f;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        df[d] = xi[d] - X[j * DIM + d];
+        df[d] = xi[d] - __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, xg[d]), rl + u));
         r2 = fmaf(df[d], df[d], r2);
       }
       const float K = __builtin_amdgcn_exp2f(-r2 * c2);
@@ -212,8 +308,8 @@ __global__ void __launch_bounds__(NWB * 64)
 #pragma unroll
       for (int q = 0; q < MAXA; ++q) {
         if (q < na) {
-          const int b = q / alpha, c = q % alpha;
-          const uint32_t code = mb.codes[b][j * alpha + c];
+          const int b = q / alpha;
+          const uint32_t code = (uint32_t)__builtin_amdgcn_readlane((int)cg[q], rl + u);
           const float sg = __builtin_bit_cast(float, (code << 31) | 0x3f800000u);
           gij = fmaf(Wr[((int)(code >> 1) + mb.coloff[b]) * 64 + lane], sg, gij);
           gji = fmaf(wrow[colL[q]], sgL[q], gji);
@@ -274,17 +370,21 @@ __global__ void dh_reduce_kernel(const double* __restrict__ part, int64_t np, do
 }
 
 // ------------------------------------------------------------------ launch
-template <int NW, int NJ, int KCK>
+template <int NW, int NJ, int KCK, bool LDSE>
 static int run_mf(Ctx* c, int dim, const float* X, int64_t N, float c2, float shift, const SjltPass& pass,
                   float* out, int64_t ldo, float scale, int split, float* part, int gz, hipStream_t st) {
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)split, (unsigned)gz);
-  ProfScope ps(c, "mf_fwd", st);
-  switch (dim) {
-    case 1: mf_sjlt_kernel<NW, NJ, KCK, 1><<<grid, NW * 64, 0, st>>>(X, N, c2, shift, pass, out, ldo, scale, split, part); break;
-    case 2: mf_sjlt_kernel<NW, NJ, KCK, 2><<<grid, NW * 64, 0, st>>>(X, N, c2, shift, pass, out, ldo, scale, split, part); break;
-    case 3: mf_sjlt_kernel<NW, NJ, KCK, 3><<<grid, NW * 64, 0, st>>>(X, N, c2, shift, pass, out, ldo, scale, split, part); break;
-    default: mf_sjlt_kernel<NW, NJ, KCK, 4><<<grid, NW * 64, 0, st>>>(X, N, c2, shift, pass, out, ldo, scale, split, part); break;
+  const size_t shmem = (size_t)(KCK + 1) * 64 * 4 + (LDSE ? ((size_t)pass.nblk * pass.kcap + 8) * 8 : 0);
+  auto kern = dim == 1 ? mf_sjlt_kernel<NW, NJ, KCK, 1, LDSE>
+              : dim == 2 ? mf_sjlt_kernel<NW, NJ, KCK, 2, LDSE>
+              : dim == 3 ? mf_sjlt_kernel<NW, NJ, KCK, 3, LDSE> : mf_sjlt_kernel<NW, NJ, KCK, 4, LDSE>;
+  static bool attr_set[4] = {false, false, false, false};
+  if (!attr_set[dim - 1]) {
+    SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr_set[dim - 1] = true;
   }
+  ProfScope ps(c, "mf_fwd", st);
+  kern<<<grid, NW * 64, shmem, st>>>(X, N, c2, shift, pass, out, ldo, scale, split, part);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }
@@ -343,8 +443,26 @@ int launch_mf_pass(Handle* h, const sk_input* in, int b0, int b1, void* out, int
   const float scale = (float)(1.0 / sqrt((double)h->alpha));
   int rc = SK_EINVAL;
   const int kc = h->kc;
-#define SK_MF(NW_, NJ_, KC_) \
-  if (nw == NW_ && nj == NJ_ && kc == KC_) rc = run_mf<NW_, NJ_, KC_>(h->ctx, in->dim, in->X, N, c2, in->shift, pass, (float*)out, ldo, scale, split, part, gz, st); else
+  // bucket entries staged in LDS (four per thread and staging round, one chunk
+  // ahead) when every block of the pass has the same chunk region size
+  pass.nblk = nblk;
+  pass.kcap = 0;
+  bool same = true;
+  for (int b = b0; b < b1; ++b) pass.kcap = std::max(pass.kcap, sjlt_kcap(kc, h->alpha, h->blocks[b].w));
+  for (int b = b0; b < b1; ++b) same = same && sjlt_kcap(kc, h->alpha, h->blocks[b].w) == pass.kcap;
+  {
+    const int64_t lam2 = 2LL * kc * h->alpha * nblk / W;
+    pass.ms = lam2 >= 14 ? 8 : 4;
+  }
+  const bool ldse = same && (int64_t)nblk * pass.kcap <= (int64_t)nw * 64 * 8 &&
+                    (size_t)(kc + 1) * 64 * 4 + ((size_t)nblk * pass.kcap + 8) * 8 <= 160 * 1024;
+#define SK_MF(NW_, NJ_, KC_)                                                                                          \
+  if (nw == NW_ && nj == NJ_ && kc == KC_)                                                                            \
+    rc = ldse ? run_mf<NW_, NJ_, KC_, true>(h->ctx, in->dim, in->X, N, c2, in->shift, pass, (float*)out, ldo, scale, \
+                                            split, part, gz, st)                                                     \
+              : run_mf<NW_, NJ_, KC_, false>(h->ctx, in->dim, in->X, N, c2, in->shift, pass, (float*)out, ldo, scale, \
+                                             split, part, gz, st);                                                   \
+  else
   SK_MF(4, 16, 64) SK_MF(8, 16, 64) SK_MF(4, 32, 64) SK_MF(8, 32, 64)
   SK_MF(4, 16, 128) SK_MF(8, 16, 128) SK_MF(4, 32, 128) SK_MF(8, 32, 128)
   SK_MF(4, 16, 256) SK_MF(8, 16, 256) SK_MF(4, 32, 256) SK_MF(8, 32, 256) {
