@@ -156,6 +156,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 
   // staging roles.  S: a 4 x 4 block (rows 4 rg.., sources 4 kg..) transposed in
   // registers.  S' (A^T): row rt, sources 16 ht .. 16 ht + 15 (contiguous in A).
+  // S places the 16-byte source units of an LDS row XOR-swizzled by row / 16.
+  auto swz = [](int row) -> int { return TRANS ? 0 : (row >> 4) & 3; };
   const int rg = tid & 31, kg = tid >> 5;
   const int rt = tid & 127, ht = tid >> 7;
   float areg[4][4];
@@ -240,7 +242,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float x[4] = {areg[0][r], areg[1][r], areg[2][r], areg[3][r]};
-        split_store(x, (4 * rg + r) * RS + 4 * kg);
+        // 16-byte unit kg / 2 of row 4 rg + r at unit (kg / 2) ^ swz(row): the
+        // rows of one store are 4 apart, and without the swizzle 8 lanes would
+        // share each bank
+        const int row = 4 * rg + r;
+        split_store(x, row * RS + 8 * ((kg >> 1) ^ swz(row)) + 4 * (kg & 1));
       }
     } else {
 #pragma unroll
@@ -257,7 +263,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int p = 0; p < NP; ++p) __builtin_memcpy(&af[rb][p], &At[p][(32 * q + 16 * rb + lr) * RS + 8 * lk], 16);
+      for (int p = 0; p < NP; ++p) {
+        const int row = 32 * q + 16 * rb + lr;
+        __builtin_memcpy(&af[rb][p], &At[p][row * RS + 8 * (lk ^ swz(row))], 16);
+      }
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
       bf8 bfr;
