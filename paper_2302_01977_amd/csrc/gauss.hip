@@ -36,7 +36,7 @@ __device__ __forceinline__ TA aelem(const TA* __restrict__ A, int64_t lda, int64
 }
 
 template <typename TA, typename TS, bool TRANS, int NB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     gauss_f64_kernel(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n, const uint16_t* __restrict__ g,
                      int64_t ldg, int W, TS* __restrict__ S, int64_t ldS, double scale) {
   constexpr int KT = 16;
@@ -59,23 +59,32 @@ __global__ void __launch_bounds__(256)
   constexpr int KS = KT * WP / 256;
   const int sj = tid % WP, sk0 = (tid / WP) * KS;
 
-  for (int64_t k0 = 0; k0 < n; k0 += KT) {
-    double rv[KS];
+  // the draws (bf16 bits) and the A fragments of chunk k0 + KT are loaded while
+  // chunk k0 is multiplied
+  uint16_t rb[KS];
+  TA ar[4];
+  auto load_chunk = [&](int64_t k0) {
 #pragma unroll
     for (int u = 0; u < KS; ++u) {
       const int64_t k = k0 + sk0 + u;
-      rv[u] = (sj < wloc && k < n) ? bf16_bits_to_double(g[k + (int64_t)(jbase + sj) * ldg]) : 0.0;
+      rb[u] = (sj < wloc && k < n) ? g[k + (int64_t)(jbase + sj) * ldg] : (uint16_t)0;
     }
-    double af[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int64_t k = k0 + 4 * s + lk;
-      af[s] = (arow < m && k < n) ? (double)aelem<TRANS>(A, lda, arow, k) : 0.0;
+      ar[s] = (arow < m && k < n) ? aelem<TRANS>(A, lda, arow, k) : TA(0);
     }
+  };
+  if (n > 0) load_chunk(0);
+  for (int64_t k0 = 0; k0 < n; k0 += KT) {
+    double af[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) af[s] = (double)ar[s];
     __syncthreads();  // previous chunk consumed
 #pragma unroll
-    for (int u = 0; u < KS; ++u) Rl[(sk0 + u) * WP + sj] = rv[u];
+    for (int u = 0; u < KS; ++u) Rl[(sk0 + u) * WP + sj] = bf16_bits_to_double(rb[u]);
     __syncthreads();
+    if (k0 + KT < n) load_chunk(k0 + KT);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
 #pragma unroll
@@ -83,6 +92,8 @@ __global__ void __launch_bounds__(256)
         const double b = Rl[(4 * s + lk) * WP + cb * 16 + lr];
         acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s], b, acc[cb], 0, 0, 0);
       }
+      // one k-step of R fragments in flight at a time (keeps two waves per SIMD)
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 #pragma unroll
