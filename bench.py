@@ -193,6 +193,81 @@ def matrix_free_leg(api, ctx, steps, warmup):
     return out
 
 
+def precision_leg(api, ctx, reps):
+    """The n = 65536 FP32 Gaussian-kernel matrix (17.2 GB; points uniform in
+    [0,1]^3, h = 0.2, shift 1e-3) sketched to d = 512 in 8 blocks of 64 (one
+    apply and seven extensions, each a pass over A): BF16 and bf16x3 Gaussian,
+    FP32 SJLT (alpha = 8) and FP32 SRHT, against the Gaussian sketch in FP64
+    arithmetic.  Errors are against the same operator applied in FP64
+    arithmetic on the GPU: the FP64-arithmetic Gaussian kernel for the
+    Gaussian kinds, an FP64 copy of A (34 GB) for SJLT and SRHT.  SJLT and SRHT
+    are also timed with look-ahead: the same 8 blocks in 3 passes over A."""
+    import torch
+
+    import workloads
+    n, blk, nblk, alpha, seed = 65536, 64, 8, 8, workloads.OP_SEED[3]
+    A = workloads.gaussian_kernel_device(workloads.cfg3_points(n), 0.2, 1e-3, "float32")
+    torch.cuda.synchronize()
+    bytes_build = nblk * (n * n * 4 + n * blk * 4)
+
+    def build(kind, prec, M, keep=False, plan=(1,) * nblk):
+        # plan: blocks per call (the first call is the apply of one block)
+        kw = {"alpha": alpha} if kind == "sjlt" else {}
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        times = []
+        sk = None
+        for r in range(reps + 1):
+            if sk is not None:
+                sk.release()
+            torch.cuda.synchronize()
+            t0.record()
+            sk = api.Sketch(ctx, M, kind, blk, seed, prec=prec, **kw)
+            for nb in plan[1:]:
+                sk.extend(blk, nblocks=nb)
+            t1.record()
+            torch.cuda.synchronize()
+            if r:  # the first build warms up
+                times.append(t0.elapsed_time(t1))
+        S = sk.S.clone() if keep else None
+        sk.release()
+        return sum(times) / len(times), S
+
+    out = {"workload": "n=65536 FP32 Gaussian kernel (h=0.2, shift 1e-3, points in [0,1]^3), d=512 in 8 blocks "
+                       "of 64 (apply + 7 extend), SJLT alpha=8", "bytes_per_build": bytes_build}
+    base_ms, ref_g = build("gaussian", "native", A, keep=True)
+    out["gaussian_fp64_arith"] = {"ms": round(base_ms, 3), "TFLOPs": round(2.0 * n * n * blk * nblk / (base_ms * 1e-3) / 1e12, 2)}
+    for key, kind, prec in (("bf16x3", "gaussian", "bf16x3"), ("bf16", "gaussian", "bf16"),
+                            ("sjlt", "sjlt", "native"), ("srht", "srht", "native")):
+        ms, S = build(kind, prec, A, keep=True)
+        r = {"ms": round(ms, 3), "GBps": round(bytes_build / (ms * 1e-3) / 1e9, 1),
+             "speedup_vs_fp64_gaussian": round(base_ms / ms, 2)}
+        if kind == "gaussian":
+            r["rel_err_vs_fp64_arith"] = rel_err(S, ref_g)
+            r["mfma_TFLOPs"] = round((3 if prec == "bf16x3" else 1) * 2.0 * n * n * blk * nblk / (ms * 1e-3) / 1e12, 1)
+        if kind != "gaussian":
+            # look-ahead: the same 8 blocks in 3 passes over A (1, 3 and 4 blocks)
+            ms3, S3 = build(kind, prec, A, keep=True, plan=(1, 3, 4))
+            r["lookahead_3_passes"] = {"ms": round(ms3, 3), "speedup_vs_fp64_gaussian": round(base_ms / ms3, 2),
+                                       "rel_diff_vs_8_passes": rel_err(S3, S)}
+            del S3
+        out[key] = r
+        del S
+    del ref_g
+    # FP64 references of the SJLT and SRHT results (same operators, A promoted)
+    A64 = A.double()
+    del A
+    torch.cuda.empty_cache()
+    for key, kind in (("sjlt", "sjlt"), ("srht", "srht")):
+        _, S64 = build(kind, "native", A64, keep=True)
+        _, S32 = build(kind, "native", A64.float(), keep=True)
+        out[key]["rel_err_vs_fp64_arith"] = rel_err(S32, S64)
+        del S64, S32
+    del A64
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_leg(api, ctx, steps, warmup):
     """96 FP32 Gaussian-kernel matrices of uneven size (n_i log-uniform in
     [512, 8192]), SJLT alpha = 4, each grown in blocks of 64 to its own d_i in
@@ -325,6 +400,7 @@ def main():
         results["fp32_matrix"] = fp32
         results["matrix_free"] = matrix_free_leg(api, ctx, args.steps, args.warmup)
         results["batched"] = batch_leg(api, ctx, max(3, args.steps // 2), 2)
+        results["precision_65536"] = precision_leg(api, ctx, 2)
 
     # the timed step: SJLT, S and S' of the FP64 matrix
     r = results["sjlt"]

@@ -122,6 +122,32 @@ def cfg2(n=16384):
                 leaf=256, seed=OP_SEED[2], symmetric=False)
 
 
+def gaussian_kernel_device(X, h, shift, dtype="float32", bs=1024):
+    """The same matrix as ``gaussian_kernel_dense``, built on the GPU with torch:
+    FP64 evaluation (squared coordinate differences summed in coordinate order,
+    exp, shift on the diagonal), rounded once to ``dtype``.  Returns an n x n
+    column-major view (the transpose of a row-major buffer)."""
+    import torch
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    Xd = torch.from_numpy(X).cuda()
+    T = torch.empty((n, n), dtype=getattr(torch, dtype), device="cuda")  # T[j, i] = K(i, j)
+    inv = 1.0 / (2.0 * h * h)
+    for j0 in range(0, n, bs):
+        j1 = min(n, j0 + bs)
+        d2 = torch.zeros((j1 - j0, n), dtype=torch.float64, device="cuda")
+        for a in range(X.shape[1]):
+            diff = Xd[:, a][None, :] - Xd[j0:j1, a][:, None]
+            d2 += diff * diff
+        K = torch.exp(-d2 * inv)
+        if shift:
+            r = torch.arange(j1 - j0, device="cuda")
+            K[r, r + j0] += shift
+        T[j0:j1, :] = K.to(T.dtype)
+        del d2, K
+    return T.t()
+
+
 def cfg3_points(n=65536):
     return uniform_points(n, 3, DATA_SEED[3])
 
