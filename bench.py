@@ -193,6 +193,40 @@ def matrix_free_leg(api, ctx, steps, warmup):
     return out
 
 
+def hss_leg(api, ctx, reps=50):
+    """The n = 1024 FP64 Gaussian-kernel matrix of the adaptive HSS workload
+    (points in [0,1]^2 in bisection order, h = 0.5, shift 1e-2): the sketch of
+    the adaptive loop's initial width d0 + dd = 128 (an apply of 64 columns and
+    one extension of 64) per operator kind, in FP64.  The matrix (8 MB) stays
+    in cache, so these are latency figures, warm."""
+    import torch
+
+    import workloads
+    c = workloads.cfg1()
+    A = api.to_device_colmajor(c["A"])
+    out = {"workload": "n=1024 FP64 Gaussian kernel (cfg of the adaptive HSS run), d = 64 + 64"}
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    for kind in ("gaussian", "sjlt", "srht"):
+        kw = {"alpha": c["alpha"]} if kind == "sjlt" else {}
+        sk = api.Sketch(ctx, A, kind, c["d0"], c["seed"], symmetric=True, **kw)
+        sk.extend(c["dd"])
+        for i in range(3):
+            sk.rerun(c["seed"] + i)
+        torch.cuda.synchronize()
+        t0.record()
+        for i in range(reps):
+            sk.rerun(c["seed"] + i)
+        t1.record()
+        torch.cuda.synchronize()
+        out[kind] = {"ms_per_sketch": round(t0.elapsed_time(t1) / reps, 4)}
+        sk.release()
+    g = out["gaussian"]["ms_per_sketch"]
+    for kind in ("sjlt", "srht"):
+        out[kind]["speedup_vs_fp64_gaussian"] = round(g / out[kind]["ms_per_sketch"], 2)
+    return out
+
+
 def precision_leg(api, ctx, reps):
     """The n = 65536 FP32 Gaussian-kernel matrix (17.2 GB; points uniform in
     [0,1]^3, h = 0.2, shift 1e-3) sketched to d = 512 in 8 blocks of 64 (one
@@ -401,6 +435,7 @@ def main():
         results["matrix_free"] = matrix_free_leg(api, ctx, args.steps, args.warmup)
         results["batched"] = batch_leg(api, ctx, max(3, args.steps // 2), 2)
         results["precision_65536"] = precision_leg(api, ctx, 2)
+        results["hss_1024"] = hss_leg(api, ctx)
 
     # the timed step: SJLT, S and S' of the FP64 matrix
     r = results["sjlt"]
