@@ -100,7 +100,9 @@ static int run_batch(const BatchItem* items, const int2* work, int nwork, int kc
                : run_batch<T, false, NW_, NJ_, RPL_, KC_>(items, work, nwork, kcap, num_cu, launch, st); \
     return rc;                                                                                             \
   }
-#define SK_BT_NW(RPL_, KC_) SK_BT(4, 16, RPL_, KC_) SK_BT(8, 16, RPL_, KC_) SK_BT(8, 32, RPL_, KC_)
+#define SK_BT_NW(RPL_, KC_)                                                                    \
+  SK_BT(4, 16, RPL_, KC_) SK_BT(8, 16, RPL_, KC_) SK_BT(8, 32, RPL_, KC_) SK_BT(8, 8, RPL_, KC_) \
+  SK_BT(16, 4, RPL_, KC_) SK_BT(16, 8, RPL_, KC_) SK_BT(16, 16, RPL_, KC_)
 
 // 0 = launched (or prepared), 1 = shape not available, < 0 = error
 template <typename T>
@@ -124,23 +126,35 @@ static int batch_launch(int dtype, const BatchCfg& c, bool trans, const BatchIte
 }
 
 // candidate shapes for a block width: every wave owns NJ of the dd columns
-static std::vector<BatchCfg> batch_candidates(int dtype, int dd, int alpha) {
+// (fewer columns per wave = more waves per workgroup)
+static std::vector<BatchCfg> batch_candidates(int dtype, int dd, int alpha, bool need_t = true) {
   std::vector<BatchCfg> out;
-  int nw = 0, nj = 0;
-  if (dd == 64) nw = 4, nj = 16;
-  else if (dd == 128) nw = 8, nj = 16;
-  else if (dd == 256) nw = 8, nj = 32;
+  std::vector<std::pair<int, int>> wj;  // (waves, columns per wave)
+  if (dd == 64) wj = {{4, 16}, {8, 8}, {16, 4}};
+  else if (dd == 128) wj = {{8, 16}, {16, 8}};
+  else if (dd == 256) wj = {{8, 32}, {16, 16}};
   else return out;
   const int kr32[][2] = {{64, 4}, {64, 2}, {64, 1}, {128, 2}, {128, 1}, {256, 1}};
   const int kr64[][2] = {{64, 2}, {64, 1}, {128, 1}, {256, 1}};
   const int nkr = dtype == SK_F64 ? 4 : 6;
-  for (int i = 0; i < nkr; ++i) {
-    const int kc = dtype == SK_F64 ? kr64[i][0] : kr32[i][0];
-    const int rpl = dtype == SK_F64 ? kr64[i][1] : kr32[i][1];
-    if ((int64_t)kc * alpha > 32 * (int64_t)KC_MAX) continue;       // scatter staging capacity
-    if (nj * rpl * (dtype == SK_F64 ? 2 : 1) > 64) continue;       // accumulators per lane
-    if (sjlt_kcap(kc, alpha, dd) > nw * 64 * 8) continue;          // entry staging capacity
-    out.push_back(BatchCfg{kc, nw, nj, rpl});
+  for (const auto& p : wj) {
+    const int nw = p.first, nj = p.second;
+    for (int i = 0; i < nkr; ++i) {
+      const int kc = dtype == SK_F64 ? kr64[i][0] : kr32[i][0];
+      const int rpl = dtype == SK_F64 ? kr64[i][1] : kr32[i][1];
+      if ((int64_t)kc * alpha > 32 * (int64_t)KC_MAX) continue;       // scatter staging capacity
+      if (nj * rpl * (dtype == SK_F64 ? 2 : 1) > 64) continue;       // accumulators per lane
+      if (sjlt_kcap(kc, alpha, dd) > nw * 64 * 8) continue;          // entry staging capacity
+      // the tile must split evenly over the workgroup (S' moves whole blocks)
+      const bool ok = dtype == SK_F64 ? cfg_valid<double, false>(nw, rpl, kc) &&
+                                            (!need_t || cfg_valid<double, true>(nw, rpl, kc))
+                                      : cfg_valid<float, false>(nw, rpl, kc) &&
+                                            (!need_t || cfg_valid<float, true>(nw, rpl, kc));
+      if (!ok) continue;
+      if (gather_lds_bytes(dtype == SK_F64 ? 8 : 4, kc, 64 * rpl, true, 1, sjlt_kcap(kc, alpha, dd)) > 160 * 1024)
+        continue;
+      out.push_back(BatchCfg{kc, nw, nj, rpl});
+    }
   }
   return out;
 }
@@ -371,7 +385,7 @@ static int autotune(Batch* b, hipStream_t st, BatchCfg* best) {
     *best = BatchCfg{hit->second[0], hit->second[1], hit->second[2], hit->second[3]};
     return SK_OK;
   }
-  std::vector<BatchCfg> cand = batch_candidates(b->dtype, b->dd, b->alpha);
+  std::vector<BatchCfg> cand = batch_candidates(b->dtype, b->dd, b->alpha, any_t);
   SK_REQUIRE(!cand.empty(), SK_EUNSUPPORTED, "batched sketch supports block widths 64, 128 and 256");
   hipEvent_t e0, e1;
   SK_HIP(hipEventCreate(&e0));
@@ -464,8 +478,10 @@ int sketch_batch_create(sk_ctx* ctx, const sk_input* ins, int32_t count, const i
   if (!rc && (flags & SK_BATCH_AUTOTUNE)) rc = autotune(b, st, &cfg);
   if (!rc) rc = build_rounds(b, cfg, 1 << 30, st);
   if (!rc) {  // kernel attributes are set outside any capture
+    bool any_t = false;
+    for (int i = 0; i < count; ++i) any_t = any_t || outs[i].St;
     rc = batch_launch(dtype, cfg, false, nullptr, nullptr, 0, b->kcap, c->num_cu, false, st);
-    if (!rc) rc = batch_launch(dtype, cfg, true, nullptr, nullptr, 0, b->kcap, c->num_cu, false, st);
+    if (!rc && any_t) rc = batch_launch(dtype, cfg, true, nullptr, nullptr, 0, b->kcap, c->num_cu, false, st);
     if (rc == 1) {
       set_error("internal: batched shape unavailable");
       rc = SK_EINVAL;

@@ -121,6 +121,7 @@ static int dispatch(Ctx* c, const GatherCfg& cfg, const T* A, int64_t lda, int64
     SK_TRY_NW(16, 1, 256)
     SK_TRY_NW(32, 1, 256)
     SK_TRY_NW(64, 1, 256)
+    SK_TRY(16, 16, 1, 64) SK_TRY(16, 16, 1, 128) SK_TRY(16, 16, 1, 256)
   } else {
     SK_TRY_NW(16, 2, 64)
     SK_TRY_NW(16, 1, 64)
@@ -231,10 +232,10 @@ static GatherCfg choose_cfg(int dtype, int kc, int W, int g) {
     }
   c.nj = nj;
   c.nw = W / nj <= 4 ? 4 : 8;
-  // FP64 passes of 256 columns or more: 16 waves of 16 columns (fewer VGPRs
-  // per wave, twice the waves per CU; measured 0.74 -> 0.57 ms for S' at
-  // n = 16384, w = 256; slower at w = 128)
-  if (dtype == SK_F64 && c.rpl == 1 && W >= 256 && g % 16 == 0) {
+  // passes of 256 columns or more: 16 waves of 16 columns (fewer VGPRs per
+  // wave, twice the waves per CU; measured for FP64 S' at n = 16384, w = 256:
+  // 0.74 -> 0.57 ms; slower at w = 128)
+  if (c.rpl == 1 && W >= 256 && g % 16 == 0) {
     c.nj = 16;
     c.nw = 16;
   }
