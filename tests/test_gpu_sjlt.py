@@ -60,6 +60,22 @@ def test_sketch_parity(ctx, dtype, m, n, w, alpha):
     sk.release()
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("n,w,alpha", [(1536, 512, 4), (2048, 256, 8), (1100, 256, 4)])
+def test_wide_and_dense_buckets(ctx, dtype, n, w, alpha):
+    """Passes of 256 and more columns (16-wave launches), long buckets
+    (alpha = 8) and a ragged square matrix: S and S' against the oracle."""
+    api = _api()
+    A = workloads.random_dense(n, n, 17, dtype)
+    sk = api.Sketch(ctx, api.to_device_colmajor(A), "sjlt", w, 321, alpha=alpha, transpose=True)
+    torch.cuda.synchronize()
+    R = ops.sjlt_block(n, w, alpha, 0, 321)
+    A64 = A.astype(np.float64)
+    assert osk.rel_fro(sk.S.cpu().numpy(), osk.sketch(A64, R)) <= TOL[dtype]
+    assert osk.rel_fro(sk.St.cpu().numpy(), osk.sketch_t(A64, R)) <= TOL[dtype]
+    sk.release()
+
+
 def test_extension_multiblock_and_determinism(ctx):
     api = _api()
     n = 2048
