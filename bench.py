@@ -449,7 +449,7 @@ def main():
         traffic = recorded_traffic()
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "sjlt_dma_kernel (S = A R, direct-to-LDS)", "bytes_per_launch": bytes_sketch,
+                "kernel": "sjlt_gather_kernel<double, false, 16, 16, 1, 256> (S = A R launches)", "bytes_per_launch": bytes_sketch,
                 "avg_launch_ms": g["avg_ms"], "frac_of_measured_copy": round(ach / copy_gbps, 4),
                 "source_digest": sources_digest()}
     for sk in sketches.values():

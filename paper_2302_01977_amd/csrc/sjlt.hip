@@ -171,7 +171,8 @@ static DmaShape choose_dma(int dtype, int kc, int W, int g, int nblk, int kcap) 
 
 // Chunk sizes of a dense operator of width d.  S: about two entries per bucket
 // when the direct-to-LDS kernel has a shape for it (it double-buffers the tile,
-// so shorter chunks keep it in LDS), else about four.  S': the 1 KB column
+// so shorter chunks keep it in LDS), else about four (and four for FP64 from
+// 256 columns on).  S': the 1 KB column
 // chunks of the direct-to-LDS S' kernel when it applies, else (register-staged
 // kernel) about four entries per bucket in FP64, two in FP32.  kct = 0 when S'
 // shares the S tables.
@@ -196,6 +197,10 @@ static DmaShape choose_dma_t(int dtype, int kc, int W, int g, int nblk, int kcap
 void sjlt_pick_chunks(int dtype, int d, int alpha, bool want_t, int* kc, int* kct) {
   const int k2 = sjlt_chunk_for(d, alpha, 2);
   *kc = choose_dma(dtype, k2, d, d, 1, sjlt_kcap(k2, alpha, d)).nw ? k2 : sjlt_chunk_for(d, alpha, 4);
+  // FP64 from 256 columns on: the register-staged kernel with 16 waves and
+  // about four entries per bucket beats the direct-to-LDS one (n = 16384,
+  // w = 256: 0.517 against 0.569 ms), and S' shares its tables
+  if (dtype == SK_F64 && d >= 256) *kc = sjlt_chunk_for(d, alpha, 4);
   const int kd = dtype == SK_F64 ? 128 : 256;
   const int kt = choose_dma_t(dtype, kd, d, d, 1, sjlt_kcap(kd, alpha, d)).nw
                      ? kd
