@@ -3,7 +3,8 @@
 // The draws g are stored on the bfloat16 grid, column-major; the 1/sqrt(w_b)
 // scale is applied to the result.
 //
-// gauss_f64_kernel: v_mfma_f64_16x16x4_f64.  A workgroup of 4 waves owns 64 rows;
+// gauss_f64_kernel: v_mfma_f64_16x16x4_f64.  A workgroup of 4 waves owns 64 rows
+//   and a slice of the source range (split so that two workgroups fit per CU);
 //   wave q computes rows 16q..16q+15 against up to 256 columns.  A fragments are
 //   read straight from global memory (16 consecutive rows per column, coalesced);
 //   the R chunk (16 k x W, exact in FP64) is staged once per workgroup in LDS.
@@ -38,7 +39,8 @@ __device__ __forceinline__ TA aelem(const TA* __restrict__ A, int64_t lda, int64
 template <typename TA, typename TS, bool TRANS, int NB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     gauss_f64_kernel(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n, const uint16_t* __restrict__ g,
-                     int64_t ldg, int W, TS* __restrict__ S, int64_t ldS, double scale) {
+                     int64_t ldg, int W, TS* __restrict__ S, int64_t ldS, double scale, int split,
+                     TS* __restrict__ part) {
   constexpr int KT = 16;
   constexpr int WP = NB * 16;
   __shared__ double Rl[KT * WP];
@@ -75,8 +77,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
       ar[s] = (arow < m && k < n) ? aelem<TRANS>(A, lda, arow, k) : TA(0);
     }
   };
-  if (n > 0) load_chunk(0);
-  for (int64_t k0 = 0; k0 < n; k0 += KT) {
+  // this workgroup's slice of the source range, in whole chunks
+  const int64_t nK = (n + KT - 1) / KT;
+  const int64_t kb = nK * blockIdx.y / split * KT, ke = std::min<int64_t>(n, nK * (blockIdx.y + 1) / split * KT);
+  if (kb < ke) load_chunk(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += KT) {
     double af[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) af[s] = (double)ar[s];
@@ -84,7 +89,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
     for (int u = 0; u < KS; ++u) Rl[(sk0 + u) * WP + sj] = bf16_bits_to_double(rb[u]);
     __syncthreads();
-    if (k0 + KT < n) load_chunk(k0 + KT);
+    if (k0 + KT < ke) load_chunk(k0 + KT);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
 #pragma unroll
@@ -96,6 +101,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+  TS* dst = split > 1 ? part + (int64_t)blockIdx.y * m * W : S;
+  const int64_t ldd = split > 1 ? m : ldS;
+  const double sc = split > 1 ? 1.0 : scale;
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) {
     const int j = jbase + cb * 16 + lr;
@@ -104,7 +112,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     for (int v = 0; v < 4; ++v) {
       // v_mfma_f64_16x16x4f64 returns D[4 v + lane / 16][lane % 16] in item v
       const int64_t r = row0 + 4 * v + lk;
-      if (r < m) S[r + (int64_t)j * ldS] = (TS)(acc[cb][v] * scale);
+      if (r < m) dst[r + (int64_t)j * ldd] = (TS)(acc[cb][v] * sc);
     }
   }
 }
@@ -315,13 +323,34 @@ static int run_f64(Ctx* c, const TA* A, int64_t lda, int64_t m, int64_t n, const
   const int nb = std::min(16, (W + 15) / 16);
   const int nbk = nb <= 2 ? 2 : nb <= 4 ? 4 : nb <= 8 ? 8 : 16;
   const int gz = (W + nbk * 16 - 1) / (nbk * 16);
-  dim3 grid((unsigned)((m + 63) / 64), 1, (unsigned)gz);
-  ProfScope ps(c, TRANS ? "gauss_f64_t" : "gauss_f64", st);
-  if (nbk == 2) gauss_f64_kernel<TA, TS, TRANS, 2><<<grid, 256, 0, st>>>(A, lda, m, n, g, n, W, S, ldS, scale);
-  else if (nbk == 4) gauss_f64_kernel<TA, TS, TRANS, 4><<<grid, 256, 0, st>>>(A, lda, m, n, g, n, W, S, ldS, scale);
-  else if (nbk == 8) gauss_f64_kernel<TA, TS, TRANS, 8><<<grid, 256, 0, st>>>(A, lda, m, n, g, n, W, S, ldS, scale);
-  else gauss_f64_kernel<TA, TS, TRANS, 16><<<grid, 256, 0, st>>>(A, lda, m, n, g, n, W, S, ldS, scale);
-  SK_HIP(hipGetLastError());
+  // about two workgroups per CU (two waves per SIMD): split the source range
+  // when the row tiles are fewer, at least 8 chunks per slice
+  const int64_t tiles = ((m + 63) / 64) * gz;
+  const int64_t nK = (n + 15) / 16;
+  int split = 1;
+  if (tiles < 2 * (int64_t)c->num_cu)
+    split = (int)std::max<int64_t>(1, std::min<int64_t>((2 * c->num_cu + tiles - 1) / tiles, nK / 8));
+  TS* part = nullptr;
+  if (split > 1) {
+    const int rc = ensure_work(c, (size_t)split * (size_t)m * (size_t)W * sizeof(TS));
+    if (rc) return rc;
+    part = (TS*)c->work;
+  }
+  dim3 grid((unsigned)((m + 63) / 64), (unsigned)split, (unsigned)gz);
+  {
+    ProfScope ps(c, TRANS ? "gauss_f64_t" : "gauss_f64", st);
+#define SK_F64_CASE(NB_)                                                                                       \
+  if (nbk == NB_)                                                                                              \
+    gauss_f64_kernel<TA, TS, TRANS, NB_><<<grid, 256, 0, st>>>(A, lda, m, n, g, n, W, S, ldS, scale, split, part);
+    SK_F64_CASE(2) SK_F64_CASE(4) SK_F64_CASE(8) SK_F64_CASE(16)
+#undef SK_F64_CASE
+    SK_HIP(hipGetLastError());
+  }
+  if (split > 1) {
+    ProfScope ps(c, "gauss_reduce", st);
+    split_reduce_any(sizeof(TS) == 8 ? SK_F64 : SK_F32, part, split, m, W, S, ldS, scale, st);
+    SK_HIP(hipGetLastError());
+  }
   return SK_OK;
 }
 
