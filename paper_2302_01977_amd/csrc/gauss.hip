@@ -174,11 +174,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
   const bool g16 = (ldg & 7) == 0 && ((uintptr_t)g & 15) == 0;  // R pieces are 16-byte aligned
 
   // staging roles.  S: a 4 x 4 block (rows 4 rg.., sources 4 kg..) transposed in
-  // registers.  S' (A^T): row rt, sources 16 ht .. 16 ht + 15 (contiguous in A).
+  // registers.  S' (A^T): piece p = 256 u + tid is row p / 8 (a column of A),
+  // sources 4 (p mod 8) .. + 3: eight lanes read one column's 128 contiguous
+  // bytes, so a wave instruction covers 8 whole 128-byte segments.
   // S places the 16-byte source units of an LDS row XOR-swizzled by row / 16.
   auto swz = [](int row) -> int { return TRANS ? 0 : (row >> 4) & 3; };
   const int rg = tid & 31, kg = tid >> 5;
-  const int rt = tid & 127, ht = tid >> 7;
+
   float areg[4][4];
   uint32_t rreg[RV][4];
 
@@ -198,10 +200,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
         }
       }
     } else {
-      const int64_t r = row0 + rt;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int64_t k = k0 + 16 * ht + 4 * u;
+        const int pc = u * 256 + tid;
+        const int64_t r = row0 + (pc >> 3);
+        const int64_t k = k0 + 4 * (pc & 7);
         const float* p = A + k + r * lda;
         if (r < m && k + 4 <= n) {
           __builtin_memcpy(areg[u], p, 16);
@@ -269,7 +272,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
       }
     } else {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) split_store(areg[u], rt * RS + 16 * ht + 4 * u);
+      for (int u = 0; u < 4; ++u) {
+        const int pc = u * 256 + tid;
+        split_store(areg[u], (pc >> 3) * RS + 4 * (pc & 7));
+      }
     }
 #pragma unroll
     for (int u = 0; u < RV; ++u) {
