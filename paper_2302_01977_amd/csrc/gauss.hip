@@ -177,8 +177,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
   // registers.  S' (A^T): piece p = 256 u + tid is row p / 8 (a column of A),
   // sources 4 (p mod 8) .. + 3: eight lanes read one column's 128 contiguous
   // bytes, so a wave instruction covers 8 whole 128-byte segments.
-  // S places the 16-byte source units of an LDS row XOR-swizzled by row / 16.
-  auto swz = [](int row) -> int { return TRANS ? 0 : (row >> 4) & 3; };
+  // S places the 16-byte source units of an LDS row XOR-swizzled by row / 16
+  // (measured, paired: n = 32768, w = 64: 1.42 -> 1.22 ms; at w = 256 the
+  // plain layout is faster, 0.62 against 0.65 ms, and is kept there).
+  auto swz = [](int row) -> int { return (TRANS || NB > 8) ? 0 : (row >> 4) & 3; };
   const int rg = tid & 31, kg = tid >> 5;
 
   float areg[4][4];
