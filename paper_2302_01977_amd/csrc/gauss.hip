@@ -323,6 +323,172 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
   }
 }
 
+// S = A R in BF16 / bf16x3 with A and R moved by direct-to-LDS loads into rings
+// of stages (A: three 32-deep steps, R: two), so that two steps of A are in
+// flight while one is multiplied, with no prefetch registers and one barrier
+// per step.  Full tiles only (rows, sources and columns multiples of the tile;
+// A, its columns and the draws 16-byte aligned); other shapes take the
+// register-staged kernel above.  The A fragments are built in registers from
+// the raw FP32 stage (rounded / split there), so no converted copy is stored.
+// Raw A stage: 32 source columns of 512 bytes (128 rows); the 16-byte unit of
+// rows 4u..4u+3 of source k sits at unit u ^ 4 ((k / 8) mod 4), which makes the
+// fragment reads (16 rows x 4 source groups per wave instruction) conflict-free.
+// R stage: column j's 64 bytes with unit q at q ^ ((j / 4) mod 4).
+// S' (A^T) stage: 128 columns of A, 128 bytes (32 sources) each, the 16-byte
+// piece p of column c at slot p ^ ((c / 2) mod 8).
+template <int NB, bool X3, bool TRANS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    gauss_bf16_dma_kernel(const float* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                          const uint16_t* __restrict__ g, int64_t ldg, int W, float* __restrict__ S, int64_t ldS,
+                          float scale, Bf16Grid gr, float* __restrict__ part) {
+  constexpr int KT = 32;
+  constexpr int MR = 128;
+  constexpr int NP = X3 ? 3 : 1;
+  constexpr int WP = NB * 16;
+  constexpr int ABYTES = MR * KT * 4;   // raw A stage
+  constexpr int RBYTES = WP * KT * 2;   // R stage
+  constexpr int NA = 3, NR = 2;         // ring depths
+  constexpr int AUNITS = ABYTES / 1024;
+  constexpr int RUNITS = RBYTES / 1024;
+  static_assert(AUNITS % 4 == 0 && RBYTES % 1024 == 0, "whole KB per stage");
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  __attribute__((address_space(3))) char* const smem3 = (__attribute__((address_space(3))) char*)smem;
+
+  const int64_t lin = blockIdx.x;
+  int64_t tile;
+  int s;
+  {
+    const int per = 8 / gr.split;
+    const int x = (int)(lin & 7);
+    s = x / per;
+    tile = (x % per) + per * (lin >> 3);
+  }
+  if (tile >= gr.tiles) return;  // whole workgroup: no barrier is reached
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t row0 = (tile / gr.gz) * MR;
+  const int jbase = (int)(tile % gr.gz) * WP;
+  const int64_t nK = n / KT;
+  const int64_t kt0 = nK * s / gr.split, kt1 = nK * (s + 1) / gr.split;
+
+  // step kt of A into ring slot kt % NA.  S: unit u holds source columns 2u and
+  // 2u + 1; S': unit u holds columns 8u .. 8u + 7 of A
+  auto issue_a = [&](int64_t kt) {
+    char* const dst = (char*)smem3 + (int)(kt % NA) * ABYTES;
+#pragma unroll
+    for (int i = 0; i < AUNITS / 4; ++i) {
+      const int u = wave + 4 * i;
+      const float* gp;
+      if constexpr (!TRANS) {
+        const int k = 2 * u + (lane >> 5);                  // source column within the step
+        const int ur = (lane & 31) ^ (4 * ((k >> 3) & 3));  // unit of rows held by this lane's slot
+        gp = A + (row0 + 4 * ur) + (kt * KT + k) * lda;
+      } else {
+        const int c = 8 * u + (lane >> 3);                  // column of A (row of S')
+        const int pc = (lane & 7) ^ ((c >> 1) & 7);         // 16-byte piece held by this lane's slot
+        gp = A + (kt * KT + 4 * pc) + (row0 + c) * lda;
+      }
+      __builtin_amdgcn_global_load_lds((void*)gp, (__attribute__((address_space(3))) void*)(dst + u * 1024), 16, 0,
+                                       0);
+    }
+  };
+  // step kt of R into ring slot kt % NR: unit u holds columns 16u .. 16u + 15
+  auto issue_r = [&](int64_t kt) {
+    char* const dst = (char*)smem3 + NA * ABYTES + (int)(kt % NR) * RBYTES;
+    for (int u = wave; u < RUNITS; u += 4) {
+      const int j = 16 * u + (lane >> 2);
+      const int kq = (lane & 3) ^ ((j >> 2) & 3);
+      const uint16_t* gp = g + (kt * KT + 8 * kq) + (int64_t)(jbase + j) * ldg;
+      __builtin_amdgcn_global_load_lds((void*)gp, (__attribute__((address_space(3))) void*)(dst + u * 1024), 16, 0,
+                                       0);
+    }
+  };
+
+  f4 acc[2][NB];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+
+  // issue order keeps "everything but the last 4 instructions of this wave"
+  // equal to "steps up to t complete" at the top of step t: A(t+1) is always the
+  // last thing issued before step t begins, and it is 4 instructions per wave
+  if (kt0 < kt1) {
+    issue_a(kt0);
+    issue_r(kt0);
+    if (kt0 + 1 < kt1) issue_a(kt0 + 1);
+  }
+  for (int64_t kt = kt0; kt < kt1; ++kt) {
+    if (kt + 1 < kt1) __builtin_amdgcn_s_waitcnt(0xF74);  // vmcnt(4): A(kt + 1) may stay in flight
+    else __builtin_amdgcn_s_waitcnt(0xF70);               // vmcnt(0)
+    __builtin_amdgcn_s_barrier();  // every wave's loads of step kt landed; step kt - 1 is consumed
+    if (kt + 1 < kt1) issue_r(kt + 1);
+    if (kt + 2 < kt1) issue_a(kt + 2);
+    const char* const as = smem + (int)(kt % NA) * ABYTES;
+    const char* const rs = smem + NA * ABYTES + (int)(kt % NR) * RBYTES;
+    bf8 af[2][NP];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      const int r = 32 * wave + 16 * rb + lr;
+      float x[8];
+      if constexpr (!TRANS) {
+        const int pos = ((((r >> 2) ^ (4 * lk)) << 2) | (r & 3)) * 4;  // byte position in a source column
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = *(const float*)(as + (8 * lk + e) * 512 + pos);
+      } else {
+        const int f = (r >> 1) & 7;
+        __builtin_memcpy(&x[0], as + r * 128 + 16 * ((2 * lk) ^ f), 16);
+        __builtin_memcpy(&x[4], as + r * 128 + 16 * ((2 * lk + 1) ^ f), 16);
+      }
+      __bf16 p1[8], p2[8], p3[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const __bf16 h1 = (__bf16)x[e];
+        p1[e] = h1;
+        if (X3) {
+          const float r1 = x[e] - (float)h1;
+          const __bf16 h2 = (__bf16)r1;
+          p2[e] = h2;
+          p3[e] = (__bf16)(r1 - (float)h2);
+        }
+      }
+      __builtin_memcpy(&af[rb][0], p1, 16);
+      if (X3) {
+        __builtin_memcpy(&af[rb][1 % NP], p2, 16);
+        __builtin_memcpy(&af[rb][2 % NP], p3, 16);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      bf8 bfr;
+      __builtin_memcpy(&bfr, rs + (cb * 16 + lr) * 64 + 16 * (lk ^ ((lr >> 2) & 3)), 16);
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int p = NP - 1; p >= 0; --p)  // small parts first
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[rb][p], bfr, acc[rb][cb], 0, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's reads of the stages are done
+  }
+  float* dst = gr.split > 1 ? part + (int64_t)s * m * W : S;
+  const int64_t ldd = gr.split > 1 ? m : ldS;
+  const float sc = gr.split > 1 ? 1.f : scale;
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    const int j = jbase + cb * 16 + lr;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // v_mfma_f32_16x16x32_bf16 returns D[4 (lane / 16) + v][lane % 16] in item v
+        const int64_t r = row0 + 32 * wave + 16 * rb + 4 * lk + v;
+        dst[r + (int64_t)j * ldd] = acc[rb][cb][v] * sc;
+      }
+  }
+}
+
 // ------------------------------------------------------------------ launch
 template <typename TA, typename TS, bool TRANS>
 static int run_f64(Ctx* c, const TA* A, int64_t lda, int64_t m, int64_t n, const uint16_t* g, int W, TS* S,
@@ -391,7 +557,27 @@ static int run_bf16(Ctx* c, bool x3, const float* A, int64_t lda, int64_t m, int
   const int per = 8 / split;
   const int64_t nblk = 8 * ((gr.tiles + per - 1) / per);
   dim3 grid((unsigned)nblk);
-  {
+  // full tiles with 16-byte aligned A columns and draws: the direct-to-LDS kernel
+  const int WPk = nbk * 16;
+  const bool dma = m % 128 == 0 && n % 32 == 0 && W % WPk == 0 && (lda * 4) % 16 == 0 &&
+                   (uintptr_t)A % 16 == 0 && (uintptr_t)g % 16 == 0;
+  if (dma) {
+    const size_t shmem = 3 * (size_t)128 * 32 * 4 + 2 * (size_t)WPk * 32 * 2;
+    ProfScope ps(c, x3 ? (TRANS ? "gauss_bf16x3_t" : "gauss_bf16x3") : (TRANS ? "gauss_bf16_t" : "gauss_bf16"), st);
+#define SK_BFD_CASE(NB_)                                                                                      \
+  if (nbk == NB_) {                                                                                           \
+    auto kern = x3 ? gauss_bf16_dma_kernel<NB_, true, TRANS> : gauss_bf16_dma_kernel<NB_, false, TRANS>;     \
+    static bool attr_set[2] = {false, false};                                                                 \
+    if (!attr_set[x3]) {                                                                                      \
+      SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024)); \
+      attr_set[x3] = true;                                                                                    \
+    }                                                                                                         \
+    kern<<<grid, 256, shmem, st>>>(A, lda, m, n, g, n, W, S, ldS, scale, gr, part);                           \
+  }
+    SK_BFD_CASE(2) SK_BFD_CASE(4) SK_BFD_CASE(8) SK_BFD_CASE(16)
+#undef SK_BFD_CASE
+    SK_HIP(hipGetLastError());
+  } else {
     ProfScope ps(c, x3 ? (TRANS ? "gauss_bf16x3_t" : "gauss_bf16x3") : (TRANS ? "gauss_bf16_t" : "gauss_bf16"), st);
 #define SK_BF_CASE(NB_)                                                                                       \
   if (nbk == NB_) {                                                                                           \
@@ -404,6 +590,7 @@ static int run_bf16(Ctx* c, bool x3, const float* A, int64_t lda, int64_t m, int
 #undef SK_BF_CASE
     SK_HIP(hipGetLastError());
   }
+
   if (split > 1) {
     ProfScope ps(c, "gauss_reduce", st);
     split_reduce_any(SK_F32, part, split, m, W, S, ldS, (double)scale, st);

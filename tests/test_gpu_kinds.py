@@ -149,7 +149,8 @@ def test_gaussian_fp64_parity(ctx, m, n, w):
 
 @pytest.mark.parametrize("prec,tol", [("native", 1e-6), ("bf16x3", 1e-5), ("bf16", 2e-2)])
 @pytest.mark.parametrize("m,n,w", [(1024, 1024, 64), (777, 2048, 128), (256, 256, 16), (1000, 1000, 320),
-                                   (300, 300, 48), (96, 8192, 256)])
+                                   (300, 300, 48), (96, 8192, 256), (2048, 2048, 256), (1024, 4096, 128),
+                                   (512, 512, 512)])
 def test_gaussian_fp32_precisions(ctx, prec, tol, m, n, w):
     """FP32 A: FP64 arithmetic (result rounded to FP32), bf16x3 (three exact bf16
     parts, FP32 accumulation) and plain bf16, each against the FP64 oracle on the
