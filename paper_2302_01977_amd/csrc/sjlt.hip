@@ -322,7 +322,11 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
   const int ms_raw = pass.ms;
   pass.ms = std::max(pass.ms, 4);  // the register-staged gather takes 4 or 8 straight-line slots
   int split = 1;
-  if (tiles < target) split = (int)std::min<int64_t>((target + tiles - 1) / tiles, std::max(1, pass.nT / 4));
+  // slices of at least 4 chunks; at least 2 when the tiles fill under a quarter
+  // of the chip (small matrices are latency-bound)
+  const int min_chunks = tiles * 4 < target ? 2 : 4;
+  if (tiles < target)
+    split = (int)std::min<int64_t>((target + tiles - 1) / tiles, std::max(1, pass.nT / min_chunks));
   void* part = nullptr;
   if (split > 1) {
     const int rc = ensure_work(h->ctx, (size_t)split * (size_t)L * (size_t)W * esz);
@@ -347,7 +351,8 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
       const int64_t dtarget = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)dbytes) * c->num_cu;
       int dsplit = 1;
       if (dtiles < dtarget)
-        dsplit = (int)std::min<int64_t>((dtarget + dtiles - 1) / dtiles, std::max(1, pass.nT / 4));
+        dsplit = (int)std::min<int64_t>((dtarget + dtiles - 1) / dtiles,
+                                        std::max(1, pass.nT / (dtiles * 4 < dtarget ? 2 : 4)));
       SjltPass dp = pass;  // the register-staged pass below keeps its own column groups
       dp.ms = ms_raw;
       dp.ngroups = W / ds.nj;
