@@ -141,6 +141,17 @@ def cpu_baseline(A, d, alpha, seed, budget_s=12.0):
     return t_tot / reps, cores, reps
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def rel_err(x, ref):
     import torch
     return float(torch.linalg.norm((x.double() - ref.double())) / torch.linalg.norm(ref.double()))
@@ -198,7 +209,9 @@ def hss_leg(api, ctx, reps=50):
     (points in [0,1]^2 in bisection order, h = 0.5, shift 1e-2): the sketch of
     the adaptive loop's initial width d0 + dd = 128 (an apply of 64 columns and
     one extension of 64) per operator kind, in FP64.  The matrix (8 MB) stays
-    in cache, so these are latency figures, warm."""
+    in cache between back-to-back sketches, so the main figure is warm; the
+    cold one is the mean of single sketches each preceded by a 1 GiB write
+    that evicts the L2 caches and the 256 MB last-level cache."""
     import torch
 
     import workloads
@@ -207,6 +220,7 @@ def hss_leg(api, ctx, reps=50):
     out = {"workload": "n=1024 FP64 Gaussian kernel (cfg of the adaptive HSS run), d = 64 + 64"}
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
     for kind in ("gaussian", "sjlt", "srht"):
         kw = {"alpha": c["alpha"]} if kind == "sjlt" else {}
         sk = api.Sketch(ctx, A, kind, c["d0"], c["seed"], symmetric=True, **kw)
@@ -219,8 +233,18 @@ def hss_leg(api, ctx, reps=50):
             sk.rerun(c["seed"] + i)
         t1.record()
         torch.cuda.synchronize()
-        out[kind] = {"ms_per_sketch": round(t0.elapsed_time(t1) / reps, 4)}
+        warm = t0.elapsed_time(t1) / reps
+        cold = 0.0
+        for i in range(5):
+            flush.zero_()
+            t0.record()
+            sk.rerun(c["seed"] + i)
+            t1.record()
+            torch.cuda.synchronize()
+            cold += t0.elapsed_time(t1) / 5
+        out[kind] = {"ms_per_sketch": round(warm, 4), "cold_ms_per_sketch": round(cold, 4)}
         sk.release()
+    del flush
     g = out["gaussian"]["ms_per_sketch"]
     for kind in ("sjlt", "srht"):
         out[kind]["speedup_vs_fp64_gaussian"] = round(g / out[kind]["ms_per_sketch"], 2)
@@ -459,7 +483,8 @@ def main():
     if not args.no_cpu_baseline:
         t_cpu, cores, reps = cpu_baseline(A_host, d, alpha, seed)
         cpu = {"value": round(step_bytes(8) / t_cpu / 1e9, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
-               "sample": "full workload (operator + S + S', n=16384, d=256) x %d reps, %.2f s each" % (reps, t_cpu)}
+               "sample": "full workload (operator + S + S', n=16384, d=256) x %d reps, %.2f s each" % (reps, t_cpu),
+               "cpu_model": cpu_model()}
 
     out = {
         "metric": "S=AR effective GB/s & % HBM peak, SJLT/SRHT/bf16x3 vs FP64 Gaussian at 1e-6",
