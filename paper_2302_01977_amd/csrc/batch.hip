@@ -171,11 +171,10 @@ static BatchCfg batch_default(int dtype, int dd, int alpha) {
 // ------------------------------------------------------------ batch object
 struct BatchRound {
   MetaItem* d_meta = nullptr;
-  int2* d_rows = nullptr;
   int2* d_chunks = nullptr;
   BatchItem* d_items = nullptr;
   int2* d_work[2] = {nullptr, nullptr};  // S, S'
-  int nmeta = 0, nrows = 0, nchunks = 0, nwork[2] = {0, 0};
+  int nmeta = 0, nchunks = 0, nwork[2] = {0, 0};
   std::vector<MetaItem> h_meta;
   std::vector<int> meta_matrix;  // matrix of each meta item
   hipGraph_t graph = nullptr;
@@ -199,7 +198,7 @@ struct Batch {
 static void free_round(BatchRound& r) {
   if (r.gexec) (void)hipGraphExecDestroy(r.gexec);
   if (r.graph) (void)hipGraphDestroy(r.graph);
-  void* ps[] = {r.d_meta, r.d_rows, r.d_chunks, r.d_items, r.d_work[0], r.d_work[1]};
+  void* ps[] = {r.d_meta, r.d_chunks, r.d_items, r.d_work[0], r.d_work[1]};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   r = BatchRound();
@@ -253,7 +252,7 @@ static int build_rounds(Batch* b, const BatchCfg& c, int max_rounds, hipStream_t
   size_t q = 0;
   for (int r = 0; r < nr; ++r) {
     BatchRound& R = b->rounds[r];
-    std::vector<int2> rows, chunks;
+    std::vector<int2> chunks;
     std::vector<BatchItem> items;
     std::vector<std::pair<int64_t, int2>> work[2];
     for (int i = 0; i < b->count; ++i) {
@@ -278,7 +277,6 @@ static int build_rounds(Batch* b, const BatchCfg& c, int max_rounds, hipStream_t
       const int mi = (int)R.h_meta.size();
       R.h_meta.push_back(m);
       R.meta_matrix.push_back(i);
-      for (int64_t k0 = 0; k0 < n; k0 += 256) rows.push_back(make_int2(mi, (int)k0));
       for (int t = 0; t < nT; ++t) chunks.push_back(make_int2(mi, t));
       const int ms = (int64_t)c.kc * b->alpha >= 7LL * b->dd ? 8 : 4;  // straight-line slots (4 or 8)
       const sk_output& o = b->outs[i];
@@ -307,10 +305,8 @@ static int build_rounds(Batch* b, const BatchCfg& c, int max_rounds, hipStream_t
       }
     }
     R.nmeta = (int)R.h_meta.size();
-    R.nrows = (int)rows.size();
     R.nchunks = (int)chunks.size();
     if (int rc = upload(&R.d_meta, R.h_meta, st)) return rc;
-    if (int rc = upload(&R.d_rows, rows, st)) return rc;
     if (int rc = upload(&R.d_chunks, chunks, st)) return rc;
     if (int rc = upload(&R.d_items, items, st)) return rc;
     for (int tr = 0; tr < 2; ++tr) {
@@ -331,7 +327,7 @@ static int build_rounds(Batch* b, const BatchCfg& c, int max_rounds, hipStream_t
 
 // the kernels of one round, in stream order
 static int round_kernels(Batch* b, BatchRound& R, hipStream_t st) {
-  if (int rc = launch_sjlt_meta_batch(R.d_meta, R.d_rows, R.nrows, R.d_chunks, R.nchunks, b->cfg.kc, st)) return rc;
+  if (int rc = launch_sjlt_meta_batch(R.d_meta, R.d_chunks, R.nchunks, st)) return rc;
   for (int tr = 0; tr < 2; ++tr) {
     if (!R.nwork[tr]) continue;
     const int rc = batch_launch(b->dtype, b->cfg, tr == 1, R.d_items, R.d_work[tr], R.nwork[tr], b->kcap,

@@ -10,8 +10,29 @@
 
 namespace sk {
 
-__device__ __forceinline__ void hash_row(uint32_t* __restrict__ codes, int64_t k, int alpha, uint32_t wc,
-                                         uint32_t block, Key key) {
+// ---------------------------------------------------------------- SJLT tables
+// Bucket table, chunk-major: ptr[t * (w + 1) + j] = first entry of column j in
+// chunk t; slot w holds the end of the chunk's entries.  Chunk t owns the entry
+// slots [t * kcap, (t + 1) * kcap); its unused slots hold null entries (source
+// KC, sign +, a staged slot of zeros).  One workgroup of KC_MAX threads (four
+// waves) builds one chunk: it hashes the chunk's sources into LDS, then counts,
+// scans and scatters there.
+constexpr int META_WAVES = KC_MAX / 64;
+
+struct MetaLds {
+  uint32_t sc[KC_MAX * 32];       // codes of the chunk; bits 16.. later hold the rank within the wave
+  int cnt[1025];                  // per column: count, then first entry
+  int wh[META_WAVES * 1024];      // per wave and column: count, then the count of the earlier waves
+  int wsum[META_WAVES];
+};
+
+// Hash of source k0 + kk (one thread per source): for every chunk c of the
+// block an offset in [0, w/alpha) and a sign, as code = (column << 1) | negative.
+__device__ __forceinline__ void hash_chunk(MetaLds& L, uint32_t* __restrict__ codes, bool write_codes, int64_t k0,
+                                           int nk, int alpha, uint32_t wc, uint32_t block, Key key) {
+  const int kk = threadIdx.x;
+  if (kk >= nk) return;
+  const int64_t k = k0 + kk;
   const uint32_t sbits = philox(2u, block, (uint32_t)k, 0u, key.k0, key.k1).v[0];
   for (int c4 = 0; c4 < alpha; c4 += 4) {
     const U4 o = philox(1u, block, (uint32_t)k, (uint32_t)(c4 >> 2), key.k0, key.k1);
@@ -19,142 +40,112 @@ __device__ __forceinline__ void hash_row(uint32_t* __restrict__ codes, int64_t k
     for (int q = 0; q < 4; ++q) {
       const int c = c4 + q;
       if (c < alpha) {
-        const uint32_t off = mulhi(o.v[q], wc);
-        codes[k * alpha + c] = (((uint32_t)c * wc + off) << 1) | ((sbits >> c) & 1u);
+        const uint32_t code = (((uint32_t)c * wc + mulhi(o.v[q], wc)) << 1) | ((sbits >> c) & 1u);
+        L.sc[kk * alpha + c] = code;
+        if (write_codes) codes[k * alpha + c] = code;
       }
     }
   }
 }
 
-__global__ void __launch_bounds__(256) sjlt_hash_kernel(uint32_t* __restrict__ codes, int64_t n, int alpha,
-                                                        uint32_t wc, uint32_t block, Key key) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) hash_row(codes, k, alpha, wc, block, key);
-}
-
-// Bucket table, chunk-major: ptr[t * (w + 1) + j] = first entry of column j in
-// chunk t; slot w holds the end of the chunk's entries.  Chunk t owns the entry
-// slots [t * kcap, (t + 1) * kcap); its unused slots hold null entries (source
-// KC, sign +, a staged slot of zeros).  count_chunk stores the counts,
-// scan_chunk turns them into starts.
-__device__ __forceinline__ void count_chunk(const uint32_t* __restrict__ codes, int32_t* __restrict__ ptr,
-                                            int64_t n, int alpha, int w, int kc, int t, int* cnt) {
-  for (int j = threadIdx.x; j < w; j += blockDim.x) cnt[j] = 0;
+// Tables of chunk t from the codes in L.sc.  A source's rank inside its bucket
+// counts the earlier sources of the chunk in the same bucket, so every bucket
+// lists its sources in ascending order.  Within a wave the rank comes from
+// matching lanes by ballot (one round per distinct column among the wave's
+// lanes); the earlier waves contribute their per-column counts.  Column starts
+// come from a workgroup-wide exclusive scan.  Requires blockDim.x == KC_MAX and
+// w <= 1024; the caller's writes of L.sc are ordered by the first barrier.
+__device__ __forceinline__ void bucket_chunk(MetaLds& L, int nk, int alpha, int w, int kc, int kcap, int t,
+                                             int32_t* __restrict__ ptr, int32_t* __restrict__ ent) {
+  const int kk = threadIdx.x, lane = kk & 63, wv = kk >> 6;
+  for (int j = kk; j < META_WAVES * w; j += KC_MAX) L.wh[j] = 0;
+  for (int e = kk; e < kcap; e += KC_MAX) ent[(int64_t)t * kcap + e] = kc << 1;  // null entries
   __syncthreads();
-  const int64_t k0 = (int64_t)t * kc;
-  const int nk = (int)min((int64_t)kc, n - k0);
-  for (int e = threadIdx.x; e < nk * alpha; e += blockDim.x) atomicAdd(&cnt[codes[k0 * alpha + e] >> 1], 1);
-  __syncthreads();
-  for (int j = threadIdx.x; j <= w; j += blockDim.x)
-    ptr[(int64_t)t * (w + 1) + j] = j < w ? cnt[j] : 0;
-}
-
-__global__ void __launch_bounds__(256) sjlt_count_kernel(const uint32_t* __restrict__ codes,
-                                                         int32_t* __restrict__ ptr, int64_t n, int alpha,
-                                                         int w, int kc) {
-  __shared__ int cnt[1024];
-  count_chunk(codes, ptr, n, alpha, w, kc, blockIdx.x, cnt);
-}
-
-// Exclusive scan of chunk t's w + 1 counts, offset by the chunk's region
-// start (thread 0 walks the row in order).
-__device__ __forceinline__ void scan_chunk(int32_t* __restrict__ ptr, int w, int kcap, int t) {
-  if (threadIdx.x != 0) return;
-  int32_t* row = ptr + (int64_t)t * (w + 1);
-  int32_t run = (int32_t)t * kcap;
-  for (int j = 0; j <= w; ++j) {
-    const int32_t c = row[j];
-    row[j] = run;
-    run += c;
-  }
-}
-
-__global__ void __launch_bounds__(64) chunk_scan_kernel(int32_t* __restrict__ ptr, int w, int kcap) {
-  scan_chunk(ptr, w, kcap, blockIdx.x);
-}
-
-// One thread per source of chunk t; a source's rank inside its bucket counts the
-// earlier sources of the chunk in the same bucket, so every bucket lists its
-// sources in ascending order.
-__device__ __forceinline__ void scatter_chunk(const uint32_t* __restrict__ codes, const int32_t* __restrict__ ptr,
-                                              int32_t* __restrict__ ent, int64_t n, int alpha, int w, int kc,
-                                              int kcap, int t, uint32_t* sc) {
-  const int kk = threadIdx.x;
-  const int64_t k0 = (int64_t)t * kc;
-  const int nk = (int)min((int64_t)kc, n - k0);
-  for (int e = threadIdx.x; e < nk * alpha; e += blockDim.x) sc[e] = codes[k0 * alpha + e];
-  for (int e = threadIdx.x; e < kcap; e += blockDim.x) ent[(int64_t)t * kcap + e] = kc << 1;  // null entries
-  __syncthreads();
-  if (kk >= nk) return;
+  const bool act = kk < nk;
+  const uint64_t below = (1ull << lane) - 1ull;
   for (int c = 0; c < alpha; ++c) {
-    const uint32_t code = sc[kk * alpha + c];
-    const uint32_t col = code >> 1;
-    int rank = 0;
-    for (int q = 0; q < kk; ++q) rank += (sc[q * alpha + c] >> 1) == col;
-    ent[ptr[(int64_t)t * (w + 1) + col] + rank] = (kk << 1) | (int)(code & 1u);
+    const uint32_t col = act ? (L.sc[kk * alpha + c] >> 1) : 0xFFFFFFFFu;
+    uint64_t todo = __ballot(act);
+    uint32_t r = 0;
+    while (todo) {
+      const int lead = __builtin_ctzll(todo);
+      const uint32_t lc = __builtin_amdgcn_readlane(col, lead);
+      const uint64_t same = __ballot(col == lc);
+      if (col == lc) r = (uint32_t)__popcll(same & below);
+      if (lane == lead) L.wh[wv * w + lc] = __popcll(same);  // chunks c own disjoint columns
+      todo &= ~same;
+    }
+    if (act) L.sc[kk * alpha + c] |= r << 16;
+  }
+  __syncthreads();
+  // per column: the counts of the earlier waves (in place) and the chunk's count
+  for (int j = kk; j < w; j += KC_MAX) {
+    int run = 0;
+    for (int v = 0; v < META_WAVES; ++v) {
+      const int x = L.wh[v * w + j];
+      L.wh[v * w + j] = run;
+      run += x;
+    }
+    L.cnt[j] = run;
+  }
+  __syncthreads();
+  // exclusive scan of the w counts from the region start, four columns per thread
+  int loc[4], own = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = 4 * kk + q;
+    loc[q] = j < w ? L.cnt[j] : 0;
+    own += loc[q];
+  }
+  int inc = own;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) L.wsum[wv] = inc;
+  __syncthreads();
+  int run = t * kcap + inc - own;
+  for (int v = 0; v < wv; ++v) run += L.wsum[v];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = 4 * kk + q;
+    if (j < w) L.cnt[j] = run;
+    run += loc[q];
+  }
+  if (kk == KC_MAX - 1) L.cnt[w] = run;  // the end of the chunk's entries
+  __syncthreads();
+  for (int j = kk; j <= w; j += KC_MAX) ptr[(int64_t)t * (w + 1) + j] = L.cnt[j];
+  if (!act) return;
+  for (int c = 0; c < alpha; ++c) {
+    const uint32_t v = L.sc[kk * alpha + c];
+    const uint32_t col = (v & 0xFFFFu) >> 1;
+    ent[L.cnt[col] + L.wh[wv * w + col] + (int)(v >> 16)] = (kk << 1) | (int)(v & 1u);
   }
 }
 
-__global__ void __launch_bounds__(KC_MAX) sjlt_scatter_kernel(const uint32_t* __restrict__ codes,
-                                                              const int32_t* __restrict__ ptr,
-                                                              int32_t* __restrict__ ent, int64_t n, int alpha,
-                                                              int w, int kc, int kcap) {
-  __shared__ uint32_t sc[KC_MAX * 32];
-  scatter_chunk(codes, ptr, ent, n, alpha, w, kc, kcap, blockIdx.x, sc);
-}
-
-// ---- batched: one launch per step over the blocks of many operators; list[i]
-// = (item, row block of 256 sources) for hashing, (item, chunk) otherwise
-__global__ void __launch_bounds__(256) sjlt_hash_batch(const MetaItem* __restrict__ items,
-                                                       const int2* __restrict__ list) {
+// Batched: one workgroup per (item, chunk) of every operator block of a round.
+__global__ void __launch_bounds__(KC_MAX) sjlt_meta_batch(const MetaItem* __restrict__ items,
+                                                          const int2* __restrict__ list) {
+  __shared__ MetaLds L;
   const int2 l = list[blockIdx.x];
   const MetaItem& m = items[l.x];
-  const int64_t k = (int64_t)l.y + threadIdx.x;
-  if (k < m.n) hash_row(m.codes, k, m.alpha, (uint32_t)(m.w / m.alpha), (uint32_t)m.block, Key{m.k0, m.k1});
+  const int64_t k0 = (int64_t)l.y * m.kc;
+  const int nk = (int)min((int64_t)m.kc, m.n - k0);
+  hash_chunk(L, m.codes, true, k0, nk, m.alpha, (uint32_t)(m.w / m.alpha), (uint32_t)m.block, Key{m.k0, m.k1});
+  bucket_chunk(L, nk, m.alpha, m.w, m.kc, m.kcap, l.y, m.ptr, m.ent);
 }
 
-__global__ void __launch_bounds__(256) sjlt_count_batch(const MetaItem* __restrict__ items,
-                                                        const int2* __restrict__ list) {
-  __shared__ int cnt[1024];
-  const int2 l = list[blockIdx.x];
-  const MetaItem& m = items[l.x];
-  count_chunk(m.codes, m.ptr, m.n, m.alpha, m.w, m.kc, l.y, cnt);
-}
-
-__global__ void __launch_bounds__(64) chunk_scan_batch(const MetaItem* __restrict__ items,
-                                                       const int2* __restrict__ list) {
-  const int2 l = list[blockIdx.x];
-  const MetaItem& m = items[l.x];
-  scan_chunk(m.ptr, m.w, m.kcap, l.y);
-}
-
-__global__ void __launch_bounds__(KC_MAX) sjlt_scatter_batch(const MetaItem* __restrict__ items,
-                                                             const int2* __restrict__ list) {
-  __shared__ uint32_t sc[KC_MAX * 32];
-  const int2 l = list[blockIdx.x];
-  const MetaItem& m = items[l.x];
-  scatter_chunk(m.codes, m.ptr, m.ent, m.n, m.alpha, m.w, m.kc, m.kcap, l.y, sc);
-}
-
-int launch_sjlt_meta_batch(const MetaItem* items, const int2* rows, int nrows, const int2* chunks, int nchunks,
-                           int kc, hipStream_t st) {
-  if (nrows == 0 || nchunks == 0) return SK_OK;
-  sjlt_hash_batch<<<nrows, 256, 0, st>>>(items, rows);
-  SK_HIP(hipGetLastError());
-  sjlt_count_batch<<<nchunks, 256, 0, st>>>(items, chunks);
-  SK_HIP(hipGetLastError());
-  chunk_scan_batch<<<nchunks, 64, 0, st>>>(items, chunks);
-  SK_HIP(hipGetLastError());
-  sjlt_scatter_batch<<<nchunks, kc, 0, st>>>(items, chunks);
+int launch_sjlt_meta_batch(const MetaItem* items, const int2* chunks, int nchunks, hipStream_t st) {
+  if (nchunks == 0) return SK_OK;
+  sjlt_meta_batch<<<nchunks, KC_MAX, 0, st>>>(items, chunks);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }
 
-// Fused generation of one block's tables: one workgroup per chunk of one table
-// set (S tables with chunk kc; optionally S' tables with chunk kct).  The
-// workgroup hashes its chunk's sources (the S set also writes the codes), then
-// counts, scans and scatters in LDS.  One launch replaces hash + count + scan +
-// scatter per set, which were dominated by launch gaps.
+// One block's tables: one workgroup per chunk of each table set (S tables with
+// chunk kc; optionally S' tables with chunk kct).  The S set also writes the
+// codes.
 struct MetaSet {
   int32_t* ptr;
   int32_t* ent;
@@ -163,64 +154,19 @@ struct MetaSet {
 
 __global__ void __launch_bounds__(KC_MAX) sjlt_meta_fused(uint32_t* __restrict__ codes, int64_t n, int alpha,
                                                           int w, uint32_t block, Key key, MetaSet s0, MetaSet s1) {
-  __shared__ uint32_t sc[KC_MAX * 32];
-  __shared__ int cnt[1025];
+  __shared__ MetaLds L;
   const bool first = (int)blockIdx.x < s0.nT;
   const MetaSet& m = first ? s0 : s1;
   const int t = first ? blockIdx.x : blockIdx.x - s0.nT;
-  const int kc = m.kc;
-  const int64_t k0 = (int64_t)t * kc;
-  const int nk = (int)min((int64_t)kc, n - k0);
-  const uint32_t wc = (uint32_t)(w / alpha);
-  // hash of the chunk's sources (same draws as hash_row)
-  for (int kk = threadIdx.x; kk < nk; kk += blockDim.x) {
-    const int64_t k = k0 + kk;
-    const uint32_t sbits = philox(2u, block, (uint32_t)k, 0u, key.k0, key.k1).v[0];
-    for (int c4 = 0; c4 < alpha; c4 += 4) {
-      const U4 o = philox(1u, block, (uint32_t)k, (uint32_t)(c4 >> 2), key.k0, key.k1);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int c = c4 + q;
-        if (c < alpha) {
-          const uint32_t code = (((uint32_t)c * wc + mulhi(o.v[q], wc)) << 1) | ((sbits >> c) & 1u);
-          sc[kk * alpha + c] = code;
-          if (first) codes[k * alpha + c] = code;
-        }
-      }
-    }
-  }
-  for (int j = threadIdx.x; j <= w; j += blockDim.x) cnt[j] = 0;
-  __syncthreads();
-  for (int e = threadIdx.x; e < nk * alpha; e += blockDim.x) atomicAdd(&cnt[sc[e] >> 1], 1);
-  __syncthreads();
-  // exclusive scan of the counts (thread 0, in order), offset by the region start
-  if (threadIdx.x == 0) {
-    int32_t run = (int32_t)t * m.kcap;
-    for (int j = 0; j < w; ++j) {
-      const int32_t c = cnt[j];
-      cnt[j] = run;
-      run += c;
-    }
-    cnt[w] = run;
-  }
-  for (int e = threadIdx.x; e < m.kcap; e += blockDim.x) m.ent[(int64_t)t * m.kcap + e] = kc << 1;  // nulls
-  __syncthreads();
-  for (int j = threadIdx.x; j <= w; j += blockDim.x) m.ptr[(int64_t)t * (w + 1) + j] = cnt[j];
-  const int kk = threadIdx.x;
-  if (kk < nk) {
-    for (int c = 0; c < alpha; ++c) {
-      const uint32_t code = sc[kk * alpha + c];
-      const uint32_t col = code >> 1;
-      int rank = 0;
-      for (int q = 0; q < kk; ++q) rank += (sc[q * alpha + c] >> 1) == col;
-      m.ent[cnt[col] + rank] = (kk << 1) | (int)(code & 1u);
-    }
-  }
+  const int64_t k0 = (int64_t)t * m.kc;
+  const int nk = (int)min((int64_t)m.kc, n - k0);
+  hash_chunk(L, codes, first, k0, nk, alpha, (uint32_t)(w / alpha), block, key);
+  bucket_chunk(L, nk, alpha, w, m.kc, m.kcap, t, m.ptr, m.ent);
 }
 
 int launch_sjlt_meta(Handle* h, Block& b, hipStream_t st) {
   const int64_t n = h->n;
-  SK_REQUIRE(b.w <= 1024 && (int64_t)h->alpha * KC_MAX <= KC_MAX * 32, SK_EINVAL, "block too wide for the tables");
+  SK_REQUIRE(b.w <= 1024 && h->alpha <= 32, SK_EINVAL, "block too wide for the tables");
   MetaSet s0{b.ptr, b.ent, h->kc, sjlt_kcap(h->kc, h->alpha, b.w), (int)((n + h->kc - 1) / h->kc)};
   MetaSet s1{nullptr, nullptr, 64, 0, 0};
   if (b.ptr_t) s1 = MetaSet{b.ptr_t, b.ent_t, h->kct, sjlt_kcap(h->kct, h->alpha, b.w), (int)((n + h->kct - 1) / h->kct)};
