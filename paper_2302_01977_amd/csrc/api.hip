@@ -198,11 +198,16 @@ static int add_block(Handle* h, int32_t w) {
   return SK_OK;
 }
 
-static int gen_block(Handle* h, int bi, hipStream_t st) {
-  Block& b = h->blocks[bi];
-  if (h->kind == SK_SJLT) return launch_sjlt_meta(h, b, st);
-  if (h->kind == SK_GAUSSIAN) return launch_gauss_meta(h, b, st);
-  return launch_srht_meta(h, b.col0, b.col0 + b.w, bi == 0, st);
+// operator metadata of blocks [b0, b1)
+static int gen_blocks(Handle* h, int b0, int b1, hipStream_t st) {
+  if (h->kind == SK_SJLT) return launch_sjlt_meta(h, b0, b1, st);
+  for (int bi = b0; bi < b1; ++bi) {
+    Block& b = h->blocks[bi];
+    const int rc = h->kind == SK_GAUSSIAN ? launch_gauss_meta(h, b, st)
+                                          : launch_srht_meta(h, b.col0, b.col0 + b.w, bi == 0, st);
+    if (rc) return rc;
+  }
+  return SK_OK;
 }
 
 static int compute_pass(Handle* h, const sk_input* in, int b0, int b1, const sk_output* out, hipStream_t st) {
@@ -362,7 +367,7 @@ int sketch_apply(sk_ctx* ctx, const sk_input* in, const sk_op_desc* op, int32_t 
     else rc = dev_alloc((float**)&h->srht_Dv, (size_t)h->n);
   }
   if (!rc) rc = add_block(h, d);
-  if (!rc) rc = gen_block(h, 0, st);
+  if (!rc) rc = gen_blocks(h, 0, 1, st);
   if (!rc) rc = compute_blocks(h, in, 0, 1, out, st);
   if (rc) {
     const std::string msg = g_err;
@@ -394,10 +399,9 @@ int sketch_extend(sk_handle* H, const sk_input* in, int32_t dd, int32_t nblocks,
   SK_HIP(hipSetDevice(h->ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const int b0 = (int)h->blocks.size();
-  for (int i = 0; i < nblocks; ++i) {
+  for (int i = 0; i < nblocks; ++i)
     if (int rc = add_block(h, dd)) return rc;
-    if (int rc = gen_block(h, b0 + i, st)) return rc;
-  }
+  if (int rc = gen_blocks(h, b0, b0 + nblocks, st)) return rc;
   return compute_blocks(h, in, b0, b0 + nblocks, out_new, st);
 }
 
@@ -410,8 +414,7 @@ int sketch_rerun(sk_handle* H, const sk_input* in, uint64_t seed, const sk_outpu
   SK_HIP(hipSetDevice(h->ctx->device));
   hipStream_t st = (hipStream_t)stream;
   h->seed = seed;
-  for (int b = 0; b < (int)h->blocks.size(); ++b)
-    if (int rc = gen_block(h, b, st)) return rc;
+  if (int rc = gen_blocks(h, 0, (int)h->blocks.size(), st)) return rc;
   return compute_blocks(h, in, 0, (int)h->blocks.size(), out, st);
 }
 

@@ -134,7 +134,8 @@ struct MetaItem {
 
 // ---- launchers (each returns SK_OK or an error code after checking the launch)
 int launch_sjlt_meta_batch(const MetaItem* items, const int2* chunks, int nchunks, hipStream_t st);
-int launch_sjlt_meta(Handle* h, Block& b, hipStream_t st);
+// bucket tables of blocks [b0, b1), as few launches as possible
+int launch_sjlt_meta(Handle* h, int b0, int b1, hipStream_t st);
 int launch_srht_meta(Handle* h, int64_t j0, int64_t j1, bool draw_D, hipStream_t st);
 int launch_gauss_meta(Handle* h, Block& b, hipStream_t st);
 

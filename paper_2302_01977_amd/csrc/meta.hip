@@ -6,6 +6,8 @@
 // that feed it, in ascending order (a counting sort, deterministic).
 // SRHT: the Rademacher diagonal D and the sampled Hadamard columns mu.
 // Gaussian: the bf16-grid draws of the block, column-major.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace sk {
@@ -143,37 +145,64 @@ int launch_sjlt_meta_batch(const MetaItem* items, const int2* chunks, int nchunk
   return SK_OK;
 }
 
-// One block's tables: one workgroup per chunk of each table set (S tables with
-// chunk kc; optionally S' tables with chunk kct).  The S set also writes the
-// codes.
+// The tables of up to META_MAX_BLOCKS blocks in one launch: one workgroup per
+// chunk of each table set of each block (S tables with chunk kc; optionally S'
+// tables with chunk kct).  The S set also writes the block's codes.
 struct MetaSet {
   int32_t* ptr;
   int32_t* ent;
   int32_t kc, kcap, nT;
 };
+constexpr int META_MAX_BLOCKS = 8;
+struct MetaBlocks {
+  uint32_t* codes[META_MAX_BLOCKS];
+  MetaSet set[META_MAX_BLOCKS][2];
+  int32_t w[META_MAX_BLOCKS];
+  uint32_t index[META_MAX_BLOCKS];
+  int32_t first[META_MAX_BLOCKS + 1];  // first workgroup of each block
+  int32_t nb;
+};
 
-__global__ void __launch_bounds__(KC_MAX) sjlt_meta_fused(uint32_t* __restrict__ codes, int64_t n, int alpha,
-                                                          int w, uint32_t block, Key key, MetaSet s0, MetaSet s1) {
+__global__ void __launch_bounds__(KC_MAX) sjlt_meta_fused(MetaBlocks mb, int64_t n, int alpha, Key key) {
   __shared__ MetaLds L;
-  const bool first = (int)blockIdx.x < s0.nT;
-  const MetaSet& m = first ? s0 : s1;
-  const int t = first ? blockIdx.x : blockIdx.x - s0.nT;
+  int b = 0;
+  while (b + 1 < mb.nb && (int)blockIdx.x >= mb.first[b + 1]) ++b;
+  int t = (int)blockIdx.x - mb.first[b];
+  const bool s0 = t < mb.set[b][0].nT;
+  if (!s0) t -= mb.set[b][0].nT;
+  const MetaSet& m = mb.set[b][s0 ? 0 : 1];
+  const int w = mb.w[b];
   const int64_t k0 = (int64_t)t * m.kc;
   const int nk = (int)min((int64_t)m.kc, n - k0);
-  hash_chunk(L, codes, first, k0, nk, alpha, (uint32_t)(w / alpha), block, key);
+  hash_chunk(L, mb.codes[b], s0, k0, nk, alpha, (uint32_t)(w / alpha), mb.index[b], key);
   bucket_chunk(L, nk, alpha, w, m.kc, m.kcap, t, m.ptr, m.ent);
 }
 
-int launch_sjlt_meta(Handle* h, Block& b, hipStream_t st) {
+int launch_sjlt_meta(Handle* h, int b0, int b1, hipStream_t st) {
   const int64_t n = h->n;
-  SK_REQUIRE(b.w <= 1024 && h->alpha <= 32, SK_EINVAL, "block too wide for the tables");
-  MetaSet s0{b.ptr, b.ent, h->kc, sjlt_kcap(h->kc, h->alpha, b.w), (int)((n + h->kc - 1) / h->kc)};
-  MetaSet s1{nullptr, nullptr, 64, 0, 0};
-  if (b.ptr_t) s1 = MetaSet{b.ptr_t, b.ent_t, h->kct, sjlt_kcap(h->kct, h->alpha, b.w), (int)((n + h->kct - 1) / h->kct)};
-  ProfScope ps(h->ctx, "sjlt_meta", st);
-  sjlt_meta_fused<<<s0.nT + s1.nT, KC_MAX, 0, st>>>(b.codes, n, h->alpha, b.w, (uint32_t)b.index, key_of(h->seed),
-                                                     s0, s1);
-  SK_HIP(hipGetLastError());
+  SK_REQUIRE(h->alpha <= 32, SK_EINVAL, "alpha too large for the tables");
+  for (int c0 = b0; c0 < b1; c0 += META_MAX_BLOCKS) {
+    MetaBlocks mb{};
+    mb.nb = std::min(META_MAX_BLOCKS, b1 - c0);
+    int grid = 0;
+    for (int i = 0; i < mb.nb; ++i) {
+      const Block& b = h->blocks[c0 + i];
+      SK_REQUIRE(b.w <= 1024, SK_EINVAL, "block too wide for the tables");
+      mb.codes[i] = b.codes;
+      mb.set[i][0] = MetaSet{b.ptr, b.ent, h->kc, sjlt_kcap(h->kc, h->alpha, b.w), (int)((n + h->kc - 1) / h->kc)};
+      mb.set[i][1] = b.ptr_t ? MetaSet{b.ptr_t, b.ent_t, h->kct, sjlt_kcap(h->kct, h->alpha, b.w),
+                                       (int)((n + h->kct - 1) / h->kct)}
+                             : MetaSet{nullptr, nullptr, 64, 0, 0};
+      mb.w[i] = b.w;
+      mb.index[i] = (uint32_t)b.index;
+      mb.first[i] = grid;
+      grid += mb.set[i][0].nT + mb.set[i][1].nT;
+    }
+    mb.first[mb.nb] = grid;
+    ProfScope ps(h->ctx, "sjlt_meta", st);
+    sjlt_meta_fused<<<grid, KC_MAX, 0, st>>>(mb, n, h->alpha, key_of(h->seed));
+    SK_HIP(hipGetLastError());
+  }
   return SK_OK;
 }
 
