@@ -208,7 +208,9 @@ def hss_leg(api, ctx, reps=50):
     """The n = 1024 FP64 Gaussian-kernel matrix of the adaptive HSS workload
     (points in [0,1]^2 in bisection order, h = 0.5, shift 1e-2): the sketch of
     the adaptive loop's initial width d0 + dd = 128 (an apply of 64 columns and
-    one extension of 64) per operator kind, in FP64.  The matrix (8 MB) stays
+    one extension of 64) per operator kind, in FP64.  At eps_r = 1e-6 the loop
+    stops at d = 64 for all three kinds (HSS ranks <= 24, no extension), so this
+    is the whole sketching work of the adaptive run.  The matrix (8 MB) stays
     in cache between back-to-back sketches, so the main figure is warm; the
     cold one is the mean of single sketches each preceded by a 1 GiB write
     that evicts the L2 caches and the 256 MB last-level cache."""
