@@ -76,6 +76,40 @@ def test_wide_and_dense_buckets(ctx, dtype, n, w, alpha):
     sk.release()
 
 
+def _device_view(A, ld, off, dtype):
+    """Column-major device copy of A with leading dimension ld >= rows, starting
+    off elements into its buffer (off = 1 leaves the columns without 16-byte
+    alignment for FP64 and FP32)."""
+    m, n = A.shape
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    buf = torch.zeros(off + ld * n, dtype=tdt, device="cuda")
+    M = buf[off:].view(n, ld).t()[:m, :]
+    M.copy_(torch.from_numpy(np.ascontiguousarray(A)).to("cuda"))
+    return M
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("m,n,w,alpha,ld,off", [(700, 700, 1024, 4, 700, 0),    # widest block
+                                                (500, 500, 256, 32, 500, 0),    # 32 nonzeros per row
+                                                (3, 1, 16, 4, 3, 0),            # one source
+                                                (1, 5, 16, 1, 1, 0),            # one row
+                                                (257, 257, 64, 4, 260, 1)])     # padded, unaligned
+def test_edge_shapes(ctx, dtype, m, n, w, alpha, ld, off):
+    """Extremes of the block width and of alpha, single rows and sources, and a
+    matrix whose columns are neither contiguous nor 16-byte aligned."""
+    api = _api()
+    A = workloads.random_dense(m, n, 23, dtype)
+    Ad = _device_view(A, ld, off, dtype)
+    sk = api.Sketch(ctx, Ad, "sjlt", w, 55, alpha=alpha, transpose=m == n)
+    torch.cuda.synchronize()
+    R = ops.sjlt_block(n, w, alpha, 0, 55)
+    A64 = A.astype(np.float64)
+    assert osk.rel_fro(sk.S.cpu().numpy(), osk.sketch(A64, R)) <= TOL[dtype]
+    if m == n:
+        assert osk.rel_fro(sk.St.cpu().numpy(), osk.sketch_t(A64, R)) <= TOL[dtype]
+    sk.release()
+
+
 def test_extension_multiblock_and_determinism(ctx):
     api = _api()
     n = 2048
@@ -152,6 +186,12 @@ def test_argument_errors(ctx):
     with pytest.raises(api.SketchError) as e:
         api.Sketch(ctx, api.to_device_colmajor(np.ones((8, 12))), "srht", 16, 1)
     assert e.value.code == -2                          # SRHT needs a power of two
+    with pytest.raises(api.SketchError) as e:
+        api.Sketch(ctx, A, "sjlt", 24, 1, alpha=4)      # widths are multiples of 16
+    assert e.value.code == -1
+    with pytest.raises(api.SketchError) as e:
+        api.Sketch(ctx, A, "sjlt", 1040, 1, alpha=4)    # wider than a block may be
+    assert e.value.code == -1
     A2 = api.to_device_colmajor(np.ones((8, 12)))
     with pytest.raises(api.SketchError):
         api.Sketch(ctx, A2, "sjlt", 16, 1, alpha=4, transpose=True)   # S' needs square A
