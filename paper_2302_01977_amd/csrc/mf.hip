@@ -20,6 +20,7 @@
 // cancellation, is accumulated in FP64 term by term.  Waves and workgroups are
 // combined in a fixed order, so the result is deterministic.
 #include <algorithm>
+#include <type_traits>
 
 #include "gather.hpp"
 #include "internal.hpp"
@@ -110,47 +111,65 @@ __global__ void __launch_bounds__(NW * 64)
   const char* tbase = (const char*)tile;
   auto LD = [&](int v) -> float { return *(const float*)(tbase + ((uint32_t)v >> 1) * 256u + lane_off); };
 
-  // the wave's sources of a chunk are src = wave + NW r (r < SPW); lane r holds
-  // the coordinates of source r, loaded one chunk ahead and broadcast with
-  // readlane (no scalar-memory round trip per source)
+  // the wave's sources of a chunk are src = wave + NW r (r < SPW); lane r
+  // loads the coordinates of source r one chunk ahead and parks them in the
+  // wave's own LDS slots (after the entries), whence the evaluation reads them
+  // as one broadcast per source: no VALU slots, and no barrier beyond the
+  // chunk's, since no other wave touches the slots
   constexpr int SPW = KCK / NW;
-  static_assert(SPW <= 64 && KCK % NW == 0, "one source per lane");
+  static_assert(SPW <= 64 && KCK % NW == 0 && DIM <= 4, "one source per lane");
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  f4* const xsl = (f4*)(smem + (size_t)(KCK + 1) * 64 * 4 + (LDSE ? ((size_t)pass.nblk * pass.kcap + 8) * 8 : 0)) +
+                  wave * SPW;
   float xs[DIM];
   auto load_xs = [&](int t) {
     const int64_t k = (int64_t)t * KCK + wave + NW * lane;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) xs[d] = (lane < SPW && k < N) ? X[k * DIM + d] : 0.f;
   };
-
-  if (t0 < t1) {
-    if (LDSE) load_meta(t0);
-    load_xs(t0);
-  }
-  for (int t = t0; t < t1; ++t) {
-    const int64_t k0 = (int64_t)t * KCK;
-    __syncthreads();  // previous chunk consumed
-    if constexpr (LDSE) store_meta();
-    float xc[DIM];
+  auto store_xs = [&]() {
+    f4 q = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) xc[d] = xs[d];
-    if (t + 1 < t1) load_xs(t + 1);
+    for (int d = 0; d < DIM; ++d) q[d] = xs[d];
+    if (lane < SPW) xsl[lane] = q;
+  };
+  // kernel entries of the chunk into the tile; only the chunk that holds the
+  // rows' own indices adds the diagonal shift
+  auto eval = [&](int64_t k0, auto diag) {
 #pragma unroll 4
     for (int r = 0; r < SPW; ++r) {
       const int src = wave + NW * r;
       const int64_t k = k0 + src;
       float v = 0.f;
       if (k < N) {
+        const f4 q = xsl[r];
         float d2 = 0.f;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-          const float df = xi[d] - __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, xc[d]), r));
+          const float df = xi[d] - q[d];
           d2 = fmaf(df, df, d2);
         }
         v = __builtin_amdgcn_exp2f(-d2 * c2);
-        if (k == i) v += shift;
+        if constexpr (decltype(diag)::value)
+          if (k == i) v += shift;
       }
       tile[src * 64 + lane] = v;
     }
+  };
+  const int tdiag = (int)(l0 / KCK);  // KCK is a multiple of 64: the tile's rows lie in one chunk
+
+  if (t0 < t1) {
+    if (LDSE) load_meta(t0);
+    load_xs(t0);
+    store_xs();
+  }
+  for (int t = t0; t < t1; ++t) {
+    const int64_t k0 = (int64_t)t * KCK;
+    __syncthreads();  // previous chunk consumed
+    if constexpr (LDSE) store_meta();
+    if (t + 1 < t1) load_xs(t + 1);
+    if (t == tdiag) eval(k0, std::true_type{});
+    else eval(k0, std::false_type{});
     if (LDSE && t + 1 < t1) load_meta(t + 1);  // in flight during the gather
     __syncthreads();
     if (active) {
@@ -160,6 +179,7 @@ __global__ void __launch_bounds__(NW * 64)
       else
         gather_chunk<float, NJ, 1, float>(ptr + (int64_t)t * prow, ent, LD, acc);
     }
+    if (t + 1 < t1) store_xs();  // this wave's evaluation of chunk t is done
   }
   if (!active || i >= N) return;
   const int64_t jc = (int64_t)g * NJ;
@@ -374,7 +394,9 @@ template <int NW, int NJ, int KCK, bool LDSE>
 static int run_mf(Ctx* c, int dim, const float* X, int64_t N, float c2, float shift, const SjltPass& pass,
                   float* out, int64_t ldo, float scale, int split, float* part, int gz, hipStream_t st) {
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)split, (unsigned)gz);
-  const size_t shmem = (size_t)(KCK + 1) * 64 * 4 + (LDSE ? ((size_t)pass.nblk * pass.kcap + 8) * 8 : 0);
+  // tile with its zero slot, (LDSE) the entries, the per-wave source coordinates
+  const size_t shmem =
+      (size_t)(KCK + 1) * 64 * 4 + (LDSE ? ((size_t)pass.nblk * pass.kcap + 8) * 8 : 0) + (size_t)KCK * 16;
   auto kern = dim == 1 ? mf_sjlt_kernel<NW, NJ, KCK, 1, LDSE>
               : dim == 2 ? mf_sjlt_kernel<NW, NJ, KCK, 2, LDSE>
               : dim == 3 ? mf_sjlt_kernel<NW, NJ, KCK, 3, LDSE> : mf_sjlt_kernel<NW, NJ, KCK, 4, LDSE>;
@@ -459,7 +481,7 @@ int launch_mf_pass(Handle* h, const sk_input* in, int b0, int b1, void* out, int
     pass.ms = lam2 >= 14 ? 8 : 4;
   }
   const bool ldse = same && (int64_t)nblk * pass.kcap <= (int64_t)nw * 64 * 8 &&
-                    (size_t)(kc + 1) * 64 * 4 + ((size_t)nblk * pass.kcap + 8) * 8 <= 160 * 1024;
+                    (size_t)(kc + 1) * 64 * 4 + ((size_t)nblk * pass.kcap + 8) * 8 + (size_t)kc * 16 <= 160 * 1024;
 #define SK_MF(NW_, NJ_, KC_)                                                                                          \
   if (nw == NW_ && nj == NJ_ && kc == KC_)                                                                            \
     rc = ldse ? run_mf<NW_, NJ_, KC_, true>(h->ctx, in->dim, in->X, N, c2, in->shift, pass, (float*)out, ldo, scale, \
