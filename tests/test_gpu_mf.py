@@ -36,7 +36,9 @@ def _f32(x):
 
 
 @pytest.mark.parametrize("N,dim,d,alpha,h,shift", [(2000, 3, 64, 4, 0.3, 0.0), (1500, 2, 256, 4, 0.5, 1e-3),
-                                                   (777, 3, 48, 8, 0.2, 0.0), (4096, 1, 32, 4, 0.1, 0.0)])
+                                                   (777, 3, 48, 8, 0.2, 0.0), (4096, 1, 32, 4, 0.1, 0.0),
+                                                   # the diagonal dominates: a misplaced shift fails at once
+                                                   (1000, 4, 64, 4, 0.05, 10.0), (3000, 3, 256, 4, 0.02, 2.5)])
 def test_forward_parity(ctx, N, dim, d, alpha, h, shift):
     api = _api()
     X = _points(N, dim, 3)
