@@ -17,7 +17,7 @@ Reported beside it, on the same GPU and in the same run:
   * the batched sketch of 96 kernel matrices of uneven size, one persistent
     graph launch per round, against per-matrix launches;
   * a measured copy bandwidth (torch copy of A), the reference for the HBM
-    counters;
+    counters, and a measured read bandwidth (torch column sums of A);
   * the FP64 CPU oracle timed on the host cores (a reported baseline).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -402,6 +402,14 @@ def main():
     copy_gbps = 2 * A.numel() * 8 / (copy_ms * 1e-3) / 1e9
     results["copy_reference"] = {"bytes_per_launch": 2 * A.numel() * 8, "ms": round(copy_ms, 4),
                                  "GBps": round(copy_gbps, 1)}
+    # measured read-only bandwidth: a column-sum reduction over A (reads A once,
+    # writes n values), the closest library kernel to the sketch's access pattern
+    colsum = torch.empty(n, dtype=A.dtype, device="cuda")
+    read_ms = time_steps(lambda i: torch.sum(A, dim=0, out=colsum), 10, 2)
+    del colsum
+    read_gbps = A.numel() * 8 / (read_ms * 1e-3) / 1e9
+    results["read_reference"] = {"bytes_per_launch": A.numel() * 8, "ms": round(read_ms, 4),
+                                 "GBps": round(read_gbps, 1), "kernel": "torch.sum over the columns of A"}
 
     kinds = ["sjlt"] if args.only_main else ["sjlt", "srht", "gaussian"]
     for kind in kinds:
@@ -477,6 +485,7 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "sjlt_gather_kernel<double, false, 16, 16, 1, 256> (S = A R launches)", "bytes_per_launch": bytes_sketch,
                 "avg_launch_ms": g["avg_ms"], "frac_of_measured_copy": round(ach / copy_gbps, 4),
+                "frac_of_measured_read": round(ach / read_gbps, 4),
                 "source_digest": sources_digest()}
     for sk in sketches.values():
         sk.release()
@@ -505,6 +514,7 @@ def main():
                                "SJLT alpha=4, d=256, S and S' per step", "n": n, "d": d, "alpha": alpha},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "pct_measured_copy": round(100 * value / copy_gbps, 2),
+        "pct_measured_read": round(100 * value / read_gbps, 2),
         "roofline": roof,
         "cpu_baseline": cpu,
         "kinds": results,
