@@ -120,7 +120,7 @@ def recorded_traffic():
         return None
 
 
-def cpu_baseline(A, d, alpha, seed, budget_s=12.0):
+def cpu_baseline(A, d, alpha, seed, budget_s=12.0, max_reps=50):
     """The FP64 oracle on the host: operator materialisation + S = A R + S' = A^T R
     for the full workload, repeated until ~budget_s of CPU work."""
     from oracle import operators as ops
@@ -131,7 +131,7 @@ def cpu_baseline(A, d, alpha, seed, budget_s=12.0):
     except Exception:
         cores = os.cpu_count() or 1
     reps, t_tot = 0, 0.0
-    while t_tot < budget_s and reps < 50:
+    while t_tot < budget_s and reps < max_reps:
         t = time.perf_counter()
         R = ops.sjlt_block(A.shape[1], d, alpha, 0, seed + reps)
         osk.sketch(A, R)
@@ -139,6 +139,30 @@ def cpu_baseline(A, d, alpha, seed, budget_s=12.0):
         t_tot += time.perf_counter() - t
         reps += 1
     return t_tot / reps, cores, reps
+
+
+def cpu_baseline_extras(A, d, alpha, seed):
+    """Beside the main figure: the same oracle step on one thread (a few
+    repetitions), and the oracle's adaptive HSS compression of the n = 1024
+    kernel matrix with its own SJLT sketches (the whole Algorithm 1 run)."""
+    import workloads
+    from oracle import hss
+    out = {}
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t1, _, r1 = cpu_baseline(A, d, alpha, seed, budget_s=4.0, max_reps=3)
+        out["one_thread"] = {"s_per_step": round(t1, 6), "reps": r1}
+    except ImportError:
+        pass
+    c = workloads.cfg1()
+    t = time.perf_counter()
+    sk = hss.OracleSketcher(c["A"], "sjlt", c["seed"], alpha=c["alpha"], symmetric=True)
+    res = hss.compress(c["A"], c["leaf"], sk, d0=c["d0"], dd=c["dd"], eps_r=c["eps_r"], eps_a=c["eps_a"],
+                       symmetric=True)
+    out["hss_1024_compress"] = {"s": round(time.perf_counter() - t, 4), "final_d": int(res.final_d),
+                                "max_rank": int(res.max_rank()), "converged": bool(res.converged)}
+    return out
 
 
 def cpu_model():
@@ -496,6 +520,7 @@ def main():
         cpu = {"value": round(step_bytes(8) / t_cpu / 1e9, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
                "sample": "full workload (operator + S + S', n=16384, d=256) x %d reps, %.2f s each" % (reps, t_cpu),
                "cpu_model": cpu_model()}
+        cpu.update(cpu_baseline_extras(A_host, d, alpha, seed))
 
     out = {
         "metric": "S=AR effective GB/s & % HBM peak, SJLT/SRHT/bf16x3 vs FP64 Gaussian at 1e-6",

@@ -35,3 +35,15 @@ def test_traffic_figure_needs_matching_sources(tmp_path, monkeypatch):
     assert bench.recorded_traffic() == 123.0
     f.write_text("source_digest: 0000000000000000\nhbm_bytes_per_launch: 123.0\n")
     assert bench.recorded_traffic() is None
+
+
+def test_cpu_baseline_extras():
+    """One-thread timing and the oracle's adaptive HSS run on the n = 1024
+    kernel workload, which stops at d = 64 at its tolerance."""
+    sys.path.insert(0, ROOT)
+    import bench
+    A = np.random.Generator(np.random.PCG64(6)).standard_normal((128, 128))
+    ex = bench.cpu_baseline_extras(A, 16, 4, 7)
+    assert ex["one_thread"]["s_per_step"] > 0
+    h = ex["hss_1024_compress"]
+    assert h["converged"] and h["final_d"] == 64 and h["s"] > 0
