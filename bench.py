@@ -56,6 +56,8 @@ def parse():
     p.add_argument("--workload", default="cauchy16k", choices=["cauchy16k"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--only-main", action="store_true", help="time the SJLT step and the copy reference only")
+    p.add_argument("--only-mf", action="store_true",
+                   help="run the matrix-free leg only and print its figures (for counter profiling)")
     return p.parse_args()
 
 
@@ -399,13 +401,19 @@ def batch_leg(api, ctx, steps, warmup):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(every box has one MI355X); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the sketch library has no multi-GPU path; "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
     import workloads
     from paper_2302_01977_amd import api
+
+    if args.only_mf:
+        ctx = api.Context(0)
+        print(json.dumps({"matrix_free": matrix_free_leg(api, ctx, args.steps, args.warmup)}))
+        ctx.close()
+        return
 
     c = workloads.cfg2()
     A_host, n, d, alpha, seed = c["A"], c["n"], c["d"], c["alpha"], c["seed"]
