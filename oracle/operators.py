@@ -18,6 +18,8 @@ these counters (all indices 0-based):
   SRHT sample mu_j (global column j)   : ctr (4, 0, j >> 2, 0), word j & 3
                                          mu = mulhi32(word, nu)
   Gaussian g_{k,j} (global column j)   : ctr (5, j, k, 0), words 0 and 1
+  SJLT graph draw, row k, step c, blk b: ctr (6, b, k, c >> 2), word c & 3
+                                         t_c = mulhi32(word, w_b - alpha + c + 1)
 """
 import math
 
@@ -58,9 +60,47 @@ def sjlt_hash(n, w, alpha, block, seed):
     return cols, signs
 
 
-def sjlt_block(n, w, alpha, block, seed):
-    """Dense FP64 SJLT block R_b (n x w): R[k, cols[k,c]] = signs[k,c] / sqrt(alpha)."""
-    cols, signs = sjlt_hash(n, w, alpha, block, seed)
+def sjlt_graph_hash(n, w, alpha, block, seed):
+    """Nonzero positions and signs of one SJLT block, graph construction.
+
+    Section 2.4.3: each row holds alpha nonzeros +-1/sqrt(alpha) at positions
+    drawn uniformly from the w columns of the block.  The text does not say
+    whether positions may repeat; the reading here is without replacement
+    (alpha distinct columns, a uniformly random alpha-subset per row), which
+    keeps exactly alpha nonzeros per row as the construction requires.
+
+    The subset is drawn with Floyd's sampling algorithm (Bentley and Floyd,
+    "A sample of brilliance", CACM 1987): for step c = 0 .. alpha-1 let
+    j = w - alpha + c and draw t uniform in [0, j]; take t unless an earlier
+    step already took it, in which case take j.  Every alpha-subset of [w] then
+    has probability 1 / C(w, alpha), with exactly alpha draws per row.  Signs use
+    the block construction's counter (2, b, k, 0), bit c.
+
+    Returns (cols, signs) of shape (n, alpha); cols[k, c] is the column chosen
+    at step c.
+    """
+    if alpha < 1 or alpha > SJLT_MAX_ALPHA or alpha > w:
+        raise ValueError("graph construction needs 1 <= alpha <= min(w, 32)")
+    key = key_from_seed(seed)
+    k = np.arange(n, dtype=np.uint64)
+    cols = np.zeros((n, alpha), dtype=np.int64)
+    for c in range(alpha):
+        j = w - alpha + c
+        word = philox4x32_10(6, block, k, c >> 2, key)[c & 3]
+        t = mulhi32(word, j + 1).astype(np.int64)
+        taken = (cols[:, :c] == t[:, None]).any(axis=1)
+        cols[:, c] = np.where(taken, j, t)
+    sw = philox4x32_10(2, block, k, 0, key)[0]
+    bits = (sw[:, None] >> np.arange(alpha, dtype=np.uint64)[None, :]) & np.uint64(1)
+    signs = 1 - 2 * bits.astype(np.int64)
+    return cols, signs
+
+
+def sjlt_block(n, w, alpha, block, seed, construction="block"):
+    """Dense FP64 SJLT block R_b (n x w): R[k, cols[k,c]] = signs[k,c] / sqrt(alpha),
+    with the positions of the block (default) or graph construction."""
+    hashf = sjlt_graph_hash if construction == "graph" else sjlt_hash
+    cols, signs = hashf(n, w, alpha, block, seed)
     R = np.zeros((n, w), dtype=np.float64)
     rows = np.repeat(np.arange(n), alpha)
     R[rows, cols.ravel()] = signs.ravel() / math.sqrt(alpha)
@@ -190,13 +230,16 @@ def gaussian_block(n, w, col0, seed):
 
 
 # ----------------------------------------------------------------- concatenation
-KINDS = ("gaussian", "sjlt", "srht")
+KINDS = ("gaussian", "sjlt", "srht", "sjlt_graph")
 
 
 def operator_block(kind, n, w, block, col0, seed, alpha=4):
-    """One block of R in FP64.  ``block`` is the block index b, ``col0`` = c_b."""
+    """One block of R in FP64.  ``block`` is the block index b, ``col0`` = c_b.
+    ``sjlt_graph`` is the SJLT operator with the graph construction."""
     if kind == "sjlt":
         return sjlt_block(n, w, alpha, block, seed)
+    if kind == "sjlt_graph":
+        return sjlt_block(n, w, alpha, block, seed, construction="graph")
     if kind == "srht":
         return srht_block(n, w, col0, seed)
     if kind == "gaussian":

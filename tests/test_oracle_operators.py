@@ -232,3 +232,56 @@ def test_gaussian_frobenius_bound_worked_value():
     bad = sum(abs(frobenius_ratio(A, ops.gaussian_block(300, dmin, 0, s)) - 1) > eps
               for s in range(400))
     assert bad / 400 <= delta
+
+
+# ------------------------------------------------------- SJLT graph construction
+@pytest.mark.parametrize("n,w,alpha", [(300, 64, 4), (257, 16, 16), (100, 256, 8), (64, 7, 1), (50, 32, 32)])
+def test_sjlt_graph_structure(n, w, alpha):
+    """Section 2.4.3, graph construction: alpha nonzeros +-1/sqrt(alpha) per row at
+    distinct columns of the block (reading: without replacement), unit row norms."""
+    cols, signs = ops.sjlt_graph_hash(n, w, alpha, 2, 31)
+    assert cols.min() >= 0 and cols.max() < w
+    assert all(len(set(r)) == alpha for r in cols.tolist())
+    assert set(np.unique(signs)) <= {-1, 1}
+    R = ops.sjlt_block(n, w, alpha, 2, 31, construction="graph")
+    assert ((R != 0).sum(1) == alpha).all()
+    assert np.allclose((R * R).sum(1), 1.0, rtol=1e-15)
+    # not the block construction: positions are not confined to chunks
+    # (alpha = w leaves one subset, all columns)
+    if 1 < alpha < w and w % alpha == 0:
+        wc = w // alpha
+        assert (cols // wc != np.arange(alpha)[None, :]).any()
+
+
+def test_sjlt_graph_subsets_uniform():
+    """Floyd's algorithm draws every alpha-subset of the w columns with probability
+    1/C(w, alpha): w = 6, alpha = 3 gives 20 subsets, counted over 60000 rows
+    (chi-square with 19 degrees of freedom, 6 sigma); every column is hit with
+    probability alpha/w."""
+    n, w, alpha = 60000, 6, 3
+    cols, signs = ops.sjlt_graph_hash(n, w, alpha, 0, 9)
+    keys = np.sort(cols, axis=1) @ np.array([36, 6, 1])
+    _, cnt = np.unique(keys, return_counts=True)
+    assert cnt.size == math.comb(w, alpha)
+    exp = n / cnt.size
+    chi2 = ((cnt - exp) ** 2 / exp).sum()
+    assert chi2 < 19 + 6 * math.sqrt(2 * 19)
+    hits = np.bincount(cols.ravel(), minlength=w) / n
+    assert np.abs(hits - alpha / w).max() < 6 * math.sqrt(0.25 / n)
+    assert abs(signs.mean()) < 6 / math.sqrt(signs.size)
+
+
+def test_sjlt_graph_jl_statistics():
+    """E ||x^T R||^2 = ||x||^2 and, with alpha distinct uniform columns per row,
+    Var = (2/w)(||x||^4 - sum x^4): the cross terms x_i x_k s_ij s_kj survive only
+    in pairs and P(j in S_i) = alpha/w for every row.  4000 seeds, 5 sigma."""
+    n, w, alpha, trials = 64, 16, 4, 4000
+    g = np.random.Generator(np.random.PCG64(1))
+    x = g.standard_normal(n)
+    x[:4] *= 6
+    nx2 = x @ x
+    vals = np.array([(lambda y: y @ y)(x @ ops.operator_block("sjlt_graph", n, w, 0, 0, 3000 + s, alpha))
+                     for s in range(trials)])
+    var = 2 / w * (nx2 ** 2 - (x ** 4).sum())
+    assert abs(vals.mean() - nx2) < 5 * math.sqrt(var / trials)
+    assert abs(vals.var() / var - 1) < 0.2

@@ -18,11 +18,11 @@ def _rand(m, n, seed):
     return np.random.Generator(np.random.PCG64(seed)).standard_normal((m, n))
 
 
-def _sjlt_AR_outer(A, n, w, alpha, block, seed):
+def _sjlt_AR_outer(A, n, w, alpha, block, seed, construction="block"):
     """Section 6.3, "Efficiently computing AR": S = sum_i A(:, i) R(i, :) by walking
     the rows of R in CRS form: add column A_i to S_j for each +1 in row i of B+,
     subtract it for each 1 in B-, and scale by s at the end."""
-    R = ops.sjlt_block(n, w, alpha, block, seed)
+    R = ops.sjlt_block(n, w, alpha, block, seed, construction)
     s, Bp, Bm = ops.sjlt_split(R)
     rp, ip = ops.crs(Bp)
     rm, im = ops.crs(Bm)
@@ -35,10 +35,10 @@ def _sjlt_AR_outer(A, n, w, alpha, block, seed):
     return s * S
 
 
-def _sjlt_AtR_inner(A, n, w, alpha, block, seed):
+def _sjlt_AtR_inner(A, n, w, alpha, block, seed, construction="block"):
     """Section 6.3, A^* R by inner products: for each column of A, signed sums over
     the CCS row lists of every column of R, scaled at the end."""
-    R = ops.sjlt_block(n, w, alpha, block, seed)
+    R = ops.sjlt_block(n, w, alpha, block, seed, construction)
     s, Bp, Bm = ops.sjlt_split(R)
     cp, jp = ops.ccs(Bp)
     cm, jm = ops.ccs(Bm)
@@ -50,13 +50,16 @@ def _sjlt_AtR_inner(A, n, w, alpha, block, seed):
     return s * St
 
 
-@pytest.mark.parametrize("m,n,w,alpha", [(37, 64, 16, 4), (20, 50, 24, 8), (64, 128, 64, 1)])
-def test_sjlt_sketch_matches_paper_algorithms(m, n, w, alpha):
+@pytest.mark.parametrize("construction", ["block", "graph"])
+@pytest.mark.parametrize("m,n,w,alpha", [(37, 64, 16, 4), (20, 50, 24, 8), (64, 128, 64, 1), (30, 40, 20, 3)])
+def test_sjlt_sketch_matches_paper_algorithms(m, n, w, alpha, construction):
+    if construction == "block" and w % alpha:
+        pytest.skip("the block construction needs alpha | w")
     A = _rand(m, n, 1)
-    R = ops.sjlt_block(n, w, alpha, 2, 99)
-    assert rel_fro(osk.sketch(A, R), _sjlt_AR_outer(A, n, w, alpha, 2, 99)) < 1e-14
+    R = ops.sjlt_block(n, w, alpha, 2, 99, construction)
+    assert rel_fro(osk.sketch(A, R), _sjlt_AR_outer(A, n, w, alpha, 2, 99, construction)) < 1e-14
     B = _rand(n, m, 2)            # S' = B^T R with B n x m (rows of R index rows of B)
-    assert rel_fro(osk.sketch_t(B, R), _sjlt_AtR_inner(B, n, w, alpha, 2, 99)) < 1e-14
+    assert rel_fro(osk.sketch_t(B, R), _sjlt_AtR_inner(B, n, w, alpha, 2, 99, construction)) < 1e-14
 
 
 def _fwht_rows(X):
@@ -169,3 +172,36 @@ def test_bf16x3_split_is_exact():
     # a single bf16 part leaves ~2^-9 relative error
     rel = np.abs(a1 - a) / np.abs(a)
     assert rel.max() <= 2.0 ** -8
+
+
+def test_kernel_row_helpers_match_full_forms_and_differences():
+    """The row-wise helpers (used for sampled rows of the N = 32768 workload) give
+    the same rows as the full forms, which are pinned above by the kernel matrix
+    and finite differences; dL/dx_i from the row helper is also checked directly
+    against central differences of the FP64 loss, so a dropped G_ji term, a
+    misplaced diagonal shift or a wrong sign in either helper fails here."""
+    g = np.random.Generator(np.random.PCG64(11))
+    N, w = 300, 32
+    X = g.random((N, 3))
+    R = ops.sjlt_block(N, w, 4, 0, 17)
+    W = g.standard_normal((N, w))
+    h, shift = 0.25, 0.7
+    rows = np.array([0, 5, 149, 150, 298, 299])
+    S = osk.kernel_sketch(X, h, R, shift=shift, block_rows=64)
+    assert rel_fro(osk.kernel_sketch_rows(X, h, R, rows, shift=shift), S[rows]) < 1e-14
+    # the shift sits on the diagonal only: rows differ from the unshifted ones by shift R(i, :)
+    d = osk.kernel_sketch_rows(X, h, R, rows, shift=shift) - osk.kernel_sketch_rows(X, h, R, rows)
+    assert np.allclose(d, shift * R[rows], rtol=0, atol=1e-14)
+    dX, _ = osk.kernel_grad(X, h, R, W, block_rows=77)
+    gr = osk.kernel_grad_rows(X, h, R, W, rows)
+    assert rel_fro(gr, dX[rows]) < 1e-13
+    coords = [(int(i), a) for i in rows for a in range(3)]
+    fd, _ = osk.finite_difference_grad(X, h, R, W, coords, step=1e-5)
+    assert np.max(np.abs(gr.reshape(-1) - fd)) < 1e-7 * max(1.0, np.max(np.abs(fd)))
+    # G_ji matters: with W R^T nonsymmetric, the one-sided sum differs
+    one_sided = np.zeros_like(gr)
+    for t, i in enumerate(rows):
+        diff = X[i][None, :] - X
+        K = np.exp(-(diff ** 2).sum(1) / (2 * h * h))
+        one_sided[t] = -((2 * (R @ W[i]) * K)[:, None] * diff).sum(0) / (h * h)
+    assert rel_fro(one_sided, gr) > 1e-2
