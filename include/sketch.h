@@ -17,6 +17,14 @@
  *   - stream is a hipStream_t (NULL = the default stream).  Compute calls only
  *     enqueue work and return; they do not synchronise the host.  Calls marked
  *     "synchronises" wait for the stream before returning.
+ *   - One stream per context at a time: the compute calls (sketch_apply,
+ *     sketch_extend, sketch_rerun, sketch_adjoint, sketch_apply_batched) keep
+ *     split-source partial sums and other scratch in the context's workspace.
+ *     Calls made through one context must be ordered on one stream (or the
+ *     caller orders their streams with events); two streams running compute
+ *     calls of one context at the same time race on that workspace.  Use one
+ *     context per concurrent stream.  A context is used by one host thread at a
+ *     time.
  *   - Operator entries are a pure function of (seed, block, index): see the
  *     counter layout in paper_2302_01977_amd/csrc/spec.hpp.  Each block is its
  *     own JL operator normalised by its own width w_b (Gaussian N(0, 1/w_b),
@@ -74,11 +82,17 @@ typedef struct {
   float shift;       /* POINTS: diagonal shift */
 } sk_input;
 
+/* SJLT constructions (section 2.4.3) */
+#define SK_SJLT_BLOCK 0 /* alpha chunks of w_b/alpha columns, one nonzero per chunk and row */
+#define SK_SJLT_GRAPH 1 /* alpha distinct columns per row drawn uniformly from the w_b columns of the block */
+
 typedef struct {
-  int32_t kind;  /* SK_GAUSSIAN, SK_SJLT or SK_SRHT */
-  int32_t alpha; /* SJLT: nonzeros per row, 1..32, must divide every block width */
-  int32_t prec;  /* SK_PREC_* (Gaussian only) */
-  int32_t flags; /* reserved, must be 0 */
+  int32_t kind;         /* SK_GAUSSIAN, SK_SJLT or SK_SRHT */
+  int32_t alpha;        /* SJLT: nonzeros per row, 1..32 (block construction: must divide every block width;
+                           graph construction: at most every block width) */
+  int32_t construction; /* SJLT: SK_SJLT_BLOCK or SK_SJLT_GRAPH; others: 0 */
+  int32_t prec;         /* SK_PREC_* (Gaussian only) */
+  int32_t flags;        /* reserved, must be 0 */
 } sk_op_desc;
 
 typedef struct {
@@ -88,10 +102,13 @@ typedef struct {
   int64_t ldSt; /* >= n when St != NULL */
 } sk_output;
 
+#define SK_INIT_PROFILE 1u /* sketch_init flag: launch timing on from the start (see sketch_profile_enable) */
+
 /* sketch_init: create a context on HIP device `device` (section 1: the sketch is
  * the preprocessing step of the compression).  *ctx receives the new context.
- * Errors: SK_EINVAL (ctx NULL or device out of range), SK_EHIP. */
-int sketch_init(sk_ctx **ctx, int32_t device);
+ * flags: 0 or SK_INIT_PROFILE; other bits are rejected.
+ * Errors: SK_EINVAL (ctx NULL, device out of range, unknown flags), SK_EHIP. */
+int sketch_init(sk_ctx **ctx, int32_t device, uint32_t flags);
 
 /* sketch_finalize: destroy a context created by sketch_init; every handle made
  * from it must have been released.  Synchronises the device.  SK_ESTATE if ctx
@@ -107,8 +124,9 @@ const char *sketch_last_error(void);
  *   (n x d; requires m == n and a nonsymmetric input)           -- section 1, eq. S <- A R
  * For SK_POINTS, S = K(X, h) R with K generated on the fly (N x N never stored).
  * *h receives a new handle owning the operator metadata (release with
- * sketch_release).  d > 0; SJLT needs alpha | d; the SJLT and SRHT kernels need
- * d % 16 == 0; SRHT needs n a power of two.  Asynchronous on `stream`.
+ * sketch_release).  d > 0; SJLT with the block construction needs alpha | d, with
+ * the graph construction alpha <= d; the SJLT and SRHT kernels need d % 16 == 0;
+ * SRHT needs n a power of two.  Asynchronous on `stream`.
  * Errors: SK_EINVAL, SK_EUNSUPPORTED, SK_ENOMEM, SK_EHIP. */
 int sketch_apply(sk_ctx *ctx, const sk_input *in, const sk_op_desc *op, int32_t d, uint64_t seed,
                  const sk_output *out, sk_handle **h, void *stream);
@@ -159,7 +177,8 @@ int sketch_get_rows(const sk_handle *h, int64_t i0, int64_t i1, int64_t j0, int6
 
 /* sketch_get_sjlt: copy the device-generated hash of SJLT block `block` to host:
  * codes[k * alpha + c] = (column inside the block << 1) | negative, for every row
- * k < n and chunk c < alpha (section 6.1: R = (B+ - B-)/sqrt(alpha)).
+ * k < n and c < alpha (section 6.1: R = (B+ - B-)/sqrt(alpha)); block
+ * construction: c is the chunk; graph construction: c is the draw step.
  * Synchronises.  SK_EINVAL if the handle is not SJLT or block is out of range. */
 int sketch_get_sjlt(const sk_handle *h, int32_t block, uint32_t *codes);
 
@@ -227,8 +246,71 @@ int sketch_batch_reseed(sk_batch *b, const uint64_t *seeds, void *stream);
  * per lane). */
 int sketch_batch_info(const sk_batch *b, int32_t *nrounds, int32_t *shape);
 
+/* sketch_batch_mode: how round `round` runs: SK_ROUND_EAGER (the batch was made
+ * without SK_BATCH_GRAPH), SK_ROUND_NOT_CAPTURED (graph mode, not run yet),
+ * SK_ROUND_GRAPH (replays its captured graph) or SK_ROUND_CAPTURE_FAILED (the
+ * runtime refused the capture or its instantiation; the round runs launch by
+ * launch with the same kernels and arguments, so results are unchanged). */
+#define SK_ROUND_EAGER 0
+#define SK_ROUND_NOT_CAPTURED 1
+#define SK_ROUND_GRAPH 2
+#define SK_ROUND_CAPTURE_FAILED 3
+int sketch_batch_mode(const sk_batch *b, int32_t round, int32_t *mode);
+
 /* sketch_batch_destroy: free the batch (synchronises the device). */
 int sketch_batch_destroy(sk_batch *b);
+
+/* sketch_apply_batched: one call for a whole batch (Algorithm 1's extension step
+ * run for many independent matrices): plans the batch exactly as
+ * sketch_batch_create (same arguments, op->kind must be SK_SJLT with the block
+ * construction and op->alpha its alpha; flags = SK_BATCH_GRAPH and/or
+ * SK_BATCH_AUTOTUNE), runs every round, frees the batch, and, when hs != NULL,
+ * stores in hs[i] a handle holding matrix i's operator (d[i] / dd blocks of
+ * width dd drawn from seeds[i], the operator sketch_apply(dd) followed by
+ * sketch_extend(dd) would draw), so that the caller can extend, query or
+ * differentiate it later; each handle must be released.  Synchronises the
+ * device.  On failure no handle is returned.
+ * Errors: as sketch_batch_create; SK_EUNSUPPORTED for other operators. */
+int sketch_apply_batched(sk_ctx *ctx, const sk_input *ins, const sk_op_desc *op, const int32_t *d, int32_t dd,
+                         const uint64_t *seeds, const sk_output *outs, int32_t count, int32_t flags, sk_handle **hs,
+                         void *stream);
+
+/* ---- operator state (checkpoint / resume) ---------------------------------
+ * An operator is a pure function of (kind, alpha, construction, precision,
+ * element type, input kind, n, seed, table chunk sizes, block widths): Algorithm
+ * 1's JL-Operator(d, n) per block, drawn from the seed.  The state holds those
+ * fields (a few hundred bytes, host memory, with a checksum); importing it
+ * regenerates every block's device metadata, so a resumed handle extends,
+ * reruns and differentiates exactly as the original would. */
+
+/* sketch_state_export: with buf == NULL, *len receives the size of the state;
+ * otherwise writes the state of h to buf (host, *len bytes available) and sets
+ * *len to the bytes written.  Host only; no device work.
+ * Errors: SK_ESTATE (bad handle), SK_EINVAL (len NULL or buffer too small). */
+int sketch_state_export(const sk_handle *h, void *buf, size_t *len);
+
+/* sketch_state_import: a new handle on ctx from a state written by
+ * sketch_state_export (host buffer of len bytes); generates its metadata on the
+ * device and synchronises.  Release with sketch_release.
+ * Errors: SK_EINVAL (not a state, wrong version, size or checksum, fields out of
+ * range), SK_EUNSUPPORTED, SK_ENOMEM, SK_EHIP. */
+int sketch_state_import(sk_ctx *ctx, const void *buf, size_t len, sk_handle **h);
+
+/* ---- test hooks (callers: test suites that exercise failure handling) ------
+ * sketch_test_hook(ctx, SK_HOOK_FAIL_ALLOC, k): the k-th device allocation made
+ *   for ctx from now on (k >= 1; 1 = the next one) fails with SK_ENOMEM as if
+ *   the device were full; k = 0 disarms.
+ * sketch_test_hook(ctx, SK_HOOK_FAIL_GRAPH, on): while on != 0, graph capture
+ *   in sketch_batch_run fails as if the runtime refused it (the round then runs
+ *   launch by launch, see sketch_batch_mode).
+ * sketch_test_poison_lds(ctx, pattern, stream): enqueue a kernel that fills the
+ *   whole 160 KB LDS of each workgroup on every CU with `pattern`, so that the
+ *   next kernels start on LDS holding those bits (checks that no kernel reads
+ *   LDS it did not write).  Asynchronous. */
+#define SK_HOOK_FAIL_ALLOC 1
+#define SK_HOOK_FAIL_GRAPH 2
+int sketch_test_hook(sk_ctx *ctx, int32_t hook, int64_t arg);
+int sketch_test_poison_lds(sk_ctx *ctx, uint32_t pattern, void *stream);
 
 #ifdef __cplusplus
 }

@@ -15,6 +15,10 @@ SK_F64, SK_F32 = 0, 1
 SK_PREC_NATIVE, SK_PREC_BF16, SK_PREC_BF16X3 = 0, 1, 2
 SK_DENSE, SK_POINTS = 0, 1
 SK_BATCH_GRAPH, SK_BATCH_AUTOTUNE = 1, 2
+SK_SJLT_BLOCK, SK_SJLT_GRAPH = 0, 1
+SK_INIT_PROFILE = 1
+SK_ROUND_EAGER, SK_ROUND_NOT_CAPTURED, SK_ROUND_GRAPH, SK_ROUND_CAPTURE_FAILED = 0, 1, 2, 3
+SK_HOOK_FAIL_ALLOC, SK_HOOK_FAIL_GRAPH = 1, 2
 
 c_i32, c_i64, c_u64, c_f32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float, ctypes.c_void_p
 
@@ -26,7 +30,7 @@ class SkInput(ctypes.Structure):
 
 
 class SkOpDesc(ctypes.Structure):
-    _fields_ = [("kind", c_i32), ("alpha", c_i32), ("prec", c_i32), ("flags", c_i32)]
+    _fields_ = [("kind", c_i32), ("alpha", c_i32), ("construction", c_i32), ("prec", c_i32), ("flags", c_i32)]
 
 
 class SkOutput(ctypes.Structure):
@@ -35,7 +39,7 @@ class SkOutput(ctypes.Structure):
 
 P = ctypes.POINTER
 _SIGS = {
-    "sketch_init": (c_i32, [P(c_vp), c_i32]),
+    "sketch_init": (c_i32, [P(c_vp), c_i32, ctypes.c_uint32]),
     "sketch_finalize": (c_i32, [c_vp]),
     "sketch_last_error": (ctypes.c_char_p, []),
     "sketch_apply": (c_i32, [c_vp, P(SkInput), P(SkOpDesc), c_i32, c_u64, P(SkOutput), P(c_vp), c_vp]),
@@ -54,6 +58,13 @@ _SIGS = {
     "sketch_batch_reseed": (c_i32, [c_vp, c_vp, c_vp]),
     "sketch_batch_info": (c_i32, [c_vp, P(c_i32), c_vp]),
     "sketch_batch_destroy": (c_i32, [c_vp]),
+    "sketch_batch_mode": (c_i32, [c_vp, c_i32, P(c_i32)]),
+    "sketch_apply_batched": (c_i32, [c_vp, P(SkInput), P(SkOpDesc), c_vp, c_i32, c_vp, P(SkOutput), c_i32, c_i32,
+                                     c_vp, c_vp]),
+    "sketch_state_export": (c_i32, [c_vp, c_vp, P(ctypes.c_size_t)]),
+    "sketch_state_import": (c_i32, [c_vp, c_vp, ctypes.c_size_t, P(c_vp)]),
+    "sketch_test_hook": (c_i32, [c_vp, c_i32, c_i64]),
+    "sketch_test_poison_lds": (c_i32, [c_vp, ctypes.c_uint32, c_vp]),
     "sketch_profile_enable": (c_i32, [c_vp, c_i32]),
     "sketch_profile_read": (c_i32, [c_vp, ctypes.c_char_p, P(ctypes.c_double), P(c_i64), c_i32]),
 }

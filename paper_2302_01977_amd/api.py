@@ -13,6 +13,7 @@ from . import _abi as abi
 
 KIND = {"gaussian": abi.SK_GAUSSIAN, "sjlt": abi.SK_SJLT, "srht": abi.SK_SRHT}
 PREC = {"native": abi.SK_PREC_NATIVE, "bf16": abi.SK_PREC_BF16, "bf16x3": abi.SK_PREC_BF16X3}
+CONSTRUCTION = {"block": abi.SK_SJLT_BLOCK, "graph": abi.SK_SJLT_GRAPH}
 
 
 class SketchError(RuntimeError):
@@ -86,11 +87,11 @@ def _output(S, St):
 class Context:
     """Per-device library context (sketch_init / sketch_finalize)."""
 
-    def __init__(self, device=0):
+    def __init__(self, device=0, profile=False):
         import weakref
         self._lib = abi.load()
         self.ptr = ctypes.c_void_p()
-        _check(self._lib.sketch_init(ctypes.byref(self.ptr), device))
+        _check(self._lib.sketch_init(ctypes.byref(self.ptr), device, abi.SK_INIT_PROFILE if profile else 0))
         self.device = device
         self._live = weakref.WeakSet()   # sketches to release before finalize
 
@@ -103,6 +104,14 @@ class Context:
         _check(self._lib.sketch_profile_read(self.ptr, name.encode(), ctypes.byref(ms), ctypes.byref(cnt),
                                              int(bool(reset))))
         return ms.value, cnt.value
+
+    def test_hook(self, hook, arg):
+        """Failure-injection hooks for tests (sketch_test_hook)."""
+        _check(self._lib.sketch_test_hook(self.ptr, hook, int(arg)))
+
+    def poison_lds(self, pattern=0x7fc00000, stream=None):
+        """Fill every CU's LDS with ``pattern`` (sketch_test_poison_lds)."""
+        _check(self._lib.sketch_test_poison_lds(self.ptr, pattern, _stream(stream)))
 
     def close(self):
         if self.ptr:
@@ -126,7 +135,7 @@ class Sketch:
     """
 
     def __init__(self, ctx, A, kind, d, seed, alpha=4, prec="native", transpose=False, symmetric=False,
-                 points=None, stream=None):
+                 points=None, stream=None, construction="block", _handle=None, _widths=None):
         self._lib = abi.load()
         self.ctx = ctx
         self.kind = kind
@@ -144,7 +153,14 @@ class Sketch:
         self.dtype = dtype
         self.device = device
         self.transpose = transpose
-        op = abi.SkOpDesc(kind=KIND[kind], alpha=alpha, prec=PREC[prec], flags=0)
+        if _handle is not None:        # an existing handle (state import, batched call)
+            self.h = _handle
+            self.widths = list(_widths)
+            self.S = self.St = None
+            ctx._live.add(self)
+            return
+        op = abi.SkOpDesc(kind=KIND[kind], alpha=alpha, construction=CONSTRUCTION[construction],
+                          prec=PREC[prec], flags=0)
         self.S = colmajor(rows, d, dtype, device)
         self.St = colmajor(self._in.n, d, dtype, device) if transpose else None
         self.h = ctypes.c_void_p()
@@ -153,6 +169,31 @@ class Sketch:
                                       _stream(stream)))
         self.widths = [d]
         ctx._live.add(self)
+
+    # -------------------------------------------------------------- state
+    def export_state(self):
+        """The operator's state (bytes): sketch_state_export."""
+        n = ctypes.c_size_t()
+        _check(self._lib.sketch_state_export(self.h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(self._lib.sketch_state_export(self.h, buf, ctypes.byref(n)))
+        return buf.raw[:n.value]
+
+    @classmethod
+    def import_state(cls, ctx, state, A=None, transpose=False, symmetric=False, points=None, widths=None):
+        """A Sketch bound to input A (or points) whose operator comes from
+        ``state`` (sketch_state_import).  S / St are None until ``rerun`` or
+        ``extend`` computes columns; ``widths`` defaults to the state's blocks."""
+        lib = abi.load()
+        h = ctypes.c_void_p()
+        buf = ctypes.create_string_buffer(state, len(state))
+        _check(lib.sketch_state_import(ctx.ptr, buf, len(state), ctypes.byref(h)))
+        d, nb = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.sketch_width(h, ctypes.byref(d), ctypes.byref(nb)))
+        # the block widths follow the state's 64-byte header as int32 values
+        ws = widths if widths is not None else list(np.frombuffer(state, dtype=np.int32, count=nb.value, offset=64))
+        return cls(ctx, A, None, d.value, 0, transpose=transpose, symmetric=symmetric, points=points,
+                   _handle=h, _widths=ws)
 
     # -------------------------------------------------------------- growth
     def extend(self, dd, nblocks=1, stream=None):
@@ -164,13 +205,17 @@ class Sketch:
         _check(self._lib.sketch_extend(self.h, ctypes.byref(self._in), dd, nblocks,
                                        ctypes.byref(_output(Sn, Stn)), _stream(stream)))
         self.widths += [dd] * nblocks
-        self.S = _hcat(self.S, Sn)
+        self.S = Sn if self.S is None else _hcat(self.S, Sn)
         if self.transpose:
-            self.St = _hcat(self.St, Stn)
+            self.St = Stn if self.St is None else _hcat(self.St, Stn)
         return Sn, Stn
 
     def rerun(self, seed, stream=None):
         """Redraw every block from ``seed`` and recompute all columns in place."""
+        if self.S is None:
+            d = sum(self.widths)
+            self.S = colmajor(self.rows, d, self.dtype, self.device)
+            self.St = colmajor(self._in.n, d, self.dtype, self.device) if self.transpose else None
         _check(self._lib.sketch_rerun(self.h, ctypes.byref(self._in), seed,
                                       ctypes.byref(_output(self.S, self.St)), _stream(stream)))
 
@@ -290,6 +335,12 @@ class Batch:
         sarr = (ctypes.c_uint64 * self.count)(*[int(x) for x in seeds])
         _check(self._lib.sketch_batch_reseed(self.h, sarr, _stream(stream)))
 
+    def mode(self, r):
+        """How round r runs (abi.SK_ROUND_*)."""
+        m = ctypes.c_int32()
+        _check(self._lib.sketch_batch_mode(self.h, r, ctypes.byref(m)))
+        return m.value
+
     def info(self):
         """(number of rounds, (chunk, waves, columns per wave, rows per lane))"""
         nr = ctypes.c_int32()
@@ -307,6 +358,35 @@ class Batch:
             self.release()
         except Exception:
             pass
+
+
+def apply_batched(ctx, mats, d, dd, seeds, alpha=4, transpose=False, graph=True, autotune=False, handles=False,
+                  stream=None):
+    """One call for a whole batch (sketch_apply_batched): returns (S list, St list,
+    Sketch list or None).  The Sketch objects hold each matrix's operator (blocks
+    of width dd) for later extension; their S / St start as None."""
+    lib = abi.load()
+    count = len(mats)
+    ins = (abi.SkInput * count)()
+    outs = (abi.SkOutput * count)()
+    S, St = [], []
+    for i, A in enumerate(mats):
+        ins[i] = dense_input(A, False)
+        S.append(colmajor(A.shape[0], d[i], A.dtype, A.device))
+        St.append(colmajor(A.shape[1], d[i], A.dtype, A.device) if transpose else None)
+        outs[i] = _output(S[i], St[i])
+    op = abi.SkOpDesc(kind=abi.SK_SJLT, alpha=alpha, construction=abi.SK_SJLT_BLOCK, prec=0, flags=0)
+    darr = (ctypes.c_int32 * count)(*[int(x) for x in d])
+    sarr = (ctypes.c_uint64 * count)(*[int(x) for x in seeds])
+    hs = (ctypes.c_void_p * count)() if handles else None
+    flags = (abi.SK_BATCH_GRAPH if graph else 0) | (abi.SK_BATCH_AUTOTUNE if autotune else 0)
+    _check(lib.sketch_apply_batched(ctx.ptr, ins, ctypes.byref(op), darr, dd, sarr, outs, count, flags, hs,
+                                    _stream(stream)))
+    sks = None
+    if handles:
+        sks = [Sketch(ctx, mats[i], None, d[i], 0, alpha=alpha, transpose=transpose,
+                      _handle=ctypes.c_void_p(hs[i]), _widths=[dd] * (d[i] // dd)) for i in range(count)]
+    return S, St, sks
 
 
 def _as_colmajor(T):

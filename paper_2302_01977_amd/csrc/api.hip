@@ -55,6 +55,21 @@ ProfScope::~ProfScope() {
   c->recs.push_back(ProfRec{name, a, b});
 }
 
+int ctx_malloc(Ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (c->fail_alloc > 0 && --c->fail_alloc == 0) {
+    set_error("device allocation of %zu bytes failed (injected by the allocation-failure test hook)", bytes);
+    return SK_ENOMEM;
+  }
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    set_error("device allocation of %zu bytes failed", bytes);
+    return SK_ENOMEM;
+  }
+  return SK_OK;
+}
+
 int ensure_work(Ctx* c, size_t bytes) {
   if (bytes <= c->work_bytes) return SK_OK;
   if (c->work) {
@@ -62,27 +77,16 @@ int ensure_work(Ctx* c, size_t bytes) {
     c->work = nullptr;
     c->work_bytes = 0;
   }
-  if (hipMalloc(&c->work, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    c->work = nullptr;
-    set_error("workspace allocation of %zu bytes failed", bytes);
-    return SK_ENOMEM;
-  }
+  if (int rc = ctx_malloc(c, &c->work, bytes)) return rc;
   c->work_bytes = bytes;
   return SK_OK;
 }
 
 template <typename P>
-static int dev_alloc(P** p, size_t count) {
+static int dev_alloc(Ctx* c, P** p, size_t count) {
   *p = nullptr;
   if (count == 0) return SK_OK;
-  if (hipMalloc((void**)p, count * sizeof(P)) != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    set_error("device allocation of %zu bytes failed", count * sizeof(P));
-    return SK_ENOMEM;
-  }
-  return SK_OK;
+  return ctx_malloc(c, (void**)p, count * sizeof(P));
 }
 
 static void free_block(Block& b) {
@@ -147,7 +151,9 @@ static int validate_out(const sk_input* in, const sk_output* out, bool want_t) {
 
 static int validate_width(const Handle* h, int32_t w) {
   SK_REQUIRE(w >= 1 && w <= 1024, SK_EINVAL, "block width must be in 1..1024 (got %d)", w);
-  if (h->kind == SK_SJLT) {
+  if (h->kind == SK_SJLT && h->construction == SK_SJLT_GRAPH) {
+    SK_REQUIRE(h->alpha <= w, SK_EINVAL, "graph construction: alpha (%d) exceeds the block width (%d)", h->alpha, w);
+  } else if (h->kind == SK_SJLT) {
     SK_REQUIRE(w % h->alpha == 0, SK_EINVAL, "alpha (%d) must divide the block width (%d)", h->alpha, w);
   }
   if (h->kind == SK_SJLT || h->kind == SK_SRHT) {
@@ -164,21 +170,21 @@ static int add_block(Handle* h, int32_t w) {
   int rc = SK_OK;
   if (h->kind == SK_SJLT) {
     const int64_t nT = (h->n + h->kc - 1) / h->kc;
-    if (!rc) rc = dev_alloc(&b.codes, (size_t)h->n * h->alpha);
-    if (!rc) rc = dev_alloc(&b.ptr, (size_t)nT * (w + 1));
-    if (!rc) rc = dev_alloc(&b.ent, (size_t)nT * sjlt_kcap(h->kc, h->alpha, w));
+    if (!rc) rc = dev_alloc(h->ctx, &b.codes, (size_t)h->n * h->alpha);
+    if (!rc) rc = dev_alloc(h->ctx, &b.ptr, (size_t)nT * (w + 1));
+    if (!rc) rc = dev_alloc(h->ctx, &b.ent, (size_t)nT * sjlt_kcap(h->kc, h->alpha, w));
     if (h->kct) {
       const int64_t nTt = (h->n + h->kct - 1) / h->kct;
-      if (!rc) rc = dev_alloc(&b.ptr_t, (size_t)nTt * (w + 1));
-      if (!rc) rc = dev_alloc(&b.ent_t, (size_t)nTt * sjlt_kcap(h->kct, h->alpha, w));
+      if (!rc) rc = dev_alloc(h->ctx, &b.ptr_t, (size_t)nTt * (w + 1));
+      if (!rc) rc = dev_alloc(h->ctx, &b.ent_t, (size_t)nTt * sjlt_kcap(h->kct, h->alpha, w));
     }
   } else if (h->kind == SK_GAUSSIAN) {
-    if (!rc) rc = dev_alloc(&b.gbf, (size_t)h->n * w);
+    if (!rc) rc = dev_alloc(h->ctx, &b.gbf, (size_t)h->n * w);
   } else if (h->kind == SK_SRHT) {
     if (h->d + w > h->mu_cap) {
       const int cap = std::max<int>(h->d + w, 2 * h->mu_cap);
       uint32_t* nmu = nullptr;
-      rc = dev_alloc(&nmu, (size_t)cap);
+      rc = dev_alloc(h->ctx, &nmu, (size_t)cap);
       if (!rc && h->srht_mu) {
         SK_HIP(hipMemcpy(nmu, h->srht_mu, sizeof(uint32_t) * h->d, hipMemcpyDeviceToDevice));
         (void)hipFree(h->srht_mu);
@@ -220,19 +226,112 @@ static int compute_pass(Handle* h, const sk_input* in, int b0, int b1, const sk_
   return launch_mf_pass(h, in, b0, b1, out->S, out->ldS, st);
 }
 
-// split a run of blocks into passes of at most MAX_PASS_BLOCKS blocks
+// split a run of blocks into passes of at most MAX_PASS_BLOCKS blocks and
+// MAX_PASS_COLS columns (a single block is at most MAX_PASS_COLS wide)
 static int compute_blocks(Handle* h, const sk_input* in, int b0, int b1, const sk_output* out, hipStream_t st) {
   int64_t col = 0;
-  for (int p0 = b0; p0 < b1; p0 += MAX_PASS_BLOCKS) {
-    const int p1 = std::min(b1, p0 + MAX_PASS_BLOCKS);
-    const size_t esz = h->dtype == SK_F64 ? 8 : 4;
+  const size_t esz = h->dtype == SK_F64 ? 8 : 4;
+  int p0 = b0;
+  while (p0 < b1) {
+    int p1 = p0;
+    int64_t w = 0;
+    while (p1 < b1 && p1 - p0 < MAX_PASS_BLOCKS && w + h->blocks[p1].w <= MAX_PASS_COLS) w += h->blocks[p1++].w;
+    SK_REQUIRE(p1 > p0, SK_EINVAL, "internal: block %d wider than a pass", p0);
     sk_output o = *out;
     o.S = (char*)out->S + (size_t)col * out->ldS * esz;
     if (out->St) o.St = (char*)out->St + (size_t)col * out->ldSt * esz;
     const int rc = compute_pass(h, in, p0, p1, &o, st);
     if (rc) return rc;
-    for (int b = p0; b < p1; ++b) col += h->blocks[b].w;
+    col += w;
+    p0 = p1;
   }
+  return SK_OK;
+}
+
+// undo add_block for blocks [b0, end) after a failed extension: the handle's
+// width and block list return to what they were before the call
+static void drop_blocks(Handle* h, int b0, int32_t d0, hipStream_t st) {
+  (void)hipStreamSynchronize(st);  // launches already queued may read the metadata
+  for (int b = (int)h->blocks.size() - 1; b >= b0; --b) free_block(h->blocks[b]);
+  h->blocks.resize(b0);
+  h->d = d0;
+}
+
+// A new handle for an operator with no blocks yet (SRHT sign arrays allocated).
+static int new_handle(Ctx* c, int kind, int alpha, int construction, int prec, int dtype, int input, int64_t n,
+                      uint64_t seed, int kc, int kct, sk_handle** out) {
+  *out = nullptr;
+  sk_handle* H = new (std::nothrow) sk_handle;
+  SK_REQUIRE(H, SK_ENOMEM, "host allocation failed");
+  Handle* h = &H->h;
+  h->ctx = c;
+  h->kind = kind;
+  h->alpha = kind == SK_SJLT ? alpha : 1;
+  h->construction = kind == SK_SJLT ? construction : 0;
+  h->prec = prec;
+  h->dtype = dtype;
+  h->input = input;
+  h->n = n;
+  h->seed = seed;
+  h->kc = kc;
+  h->kct = kct;
+  int rc = SK_OK;
+  if (kind == SK_SRHT) {
+    rc = dev_alloc(c, &h->srht_D, (size_t)n);
+    if (!rc) rc = dev_alloc(c, &h->srht_Db, (size_t)((n + 255) / 256 * 8));
+    if (!rc) {
+      if (dtype == SK_F64) rc = dev_alloc(c, (double**)&h->srht_Dv, (size_t)n);
+      else rc = dev_alloc(c, (float**)&h->srht_Dv, (size_t)n);
+    }
+  }
+  if (rc) {
+    if (h->srht_D) (void)hipFree(h->srht_D);
+    if (h->srht_Db) (void)hipFree(h->srht_Db);
+    h->magic = 0;
+    delete H;
+    return rc;
+  }
+  *out = H;
+  return SK_OK;
+}
+
+// Frees a handle that failed before it was handed out (st: the stream its
+// launches went to); keeps the error message of the failure.
+static void discard_handle(sk_handle* H, hipStream_t st) {
+  const std::string msg = g_err;
+  Handle* h = &H->h;
+  (void)hipStreamSynchronize(st);
+  for (auto& b : h->blocks) free_block(b);
+  if (h->srht_D) (void)hipFree(h->srht_D);
+  if (h->srht_Dv) (void)hipFree(h->srht_Dv);
+  if (h->srht_Db) (void)hipFree(h->srht_Db);
+  if (h->srht_mu) (void)hipFree(h->srht_mu);
+  h->magic = 0;
+  delete H;
+  g_err = msg;
+}
+
+// A handle holding the operator of blocks of the given widths drawn from
+// `seed`, metadata generated on st (nothing computed).  Used by state import
+// and by the batched call's per-matrix handles.
+int make_operator_handle(Ctx* c, int kind, int alpha, int construction, int prec, int dtype, int input, int64_t n,
+                         uint64_t seed, int kc, int kct, const int32_t* widths, int nb, sk_handle** out,
+                         hipStream_t st) {
+  sk_handle* H = nullptr;
+  if (int rc = new_handle(c, kind, alpha, construction, prec, dtype, input, n, seed, kc, kct, &H)) return rc;
+  Handle* h = &H->h;
+  int rc = SK_OK;
+  for (int b = 0; b < nb && !rc; ++b) {
+    rc = validate_width(h, widths[b]);
+    if (!rc) rc = add_block(h, widths[b]);
+  }
+  if (!rc) rc = gen_blocks(h, 0, nb, st);
+  if (rc) {
+    discard_handle(H, st);
+    return rc;
+  }
+  c->live_handles++;
+  *out = H;
   return SK_OK;
 }
 
@@ -244,15 +343,25 @@ static int check_same_input(const Handle* h, const sk_input* in) {
   return SK_OK;
 }
 
+// Fills the whole 160 KB LDS allocation of each workgroup with `pattern`
+// (test hook: later kernels on the same CUs start with those bits in LDS).
+__global__ void __launch_bounds__(1024) poison_lds_kernel(uint32_t pattern) {
+  extern __shared__ uint32_t lds_words[];
+  for (int i = threadIdx.x; i < 160 * 1024 / 4; i += blockDim.x) lds_words[i] = pattern;
+  __syncthreads();
+  asm volatile("" ::: "memory");  // the stores are the point: keep them
+}
+
 }  // namespace sk
 
 using namespace sk;
 
 extern "C" {
 
-int sketch_init(sk_ctx** ctx, int32_t device) {
+int sketch_init(sk_ctx** ctx, int32_t device, uint32_t flags) {
   SK_REQUIRE(ctx, SK_EINVAL, "ctx is NULL");
   *ctx = nullptr;
+  SK_REQUIRE((flags & ~SK_INIT_PROFILE) == 0, SK_EINVAL, "unknown sketch_init flags 0x%x", flags);
   int count = 0;
   SK_HIP(hipGetDeviceCount(&count));
   SK_REQUIRE(device >= 0 && device < count, SK_EINVAL, "device %d out of range (%d devices)", device, count);
@@ -263,6 +372,7 @@ int sketch_init(sk_ctx** ctx, int32_t device) {
   SK_REQUIRE(c, SK_ENOMEM, "host allocation failed");
   c->c.device = device;
   c->c.num_cu = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+  c->c.prof = (flags & SK_INIT_PROFILE) != 0;
   *ctx = c;
   return SK_OK;
 }
@@ -326,8 +436,13 @@ int sketch_apply(sk_ctx* ctx, const sk_input* in, const sk_op_desc* op, int32_t 
   SK_REQUIRE(op, SK_EINVAL, "operator description is NULL");
   SK_REQUIRE(op->kind >= SK_GAUSSIAN && op->kind <= SK_SRHT, SK_EINVAL, "unknown operator kind %d", op->kind);
   SK_REQUIRE(op->flags == 0, SK_EINVAL, "flags must be 0");
-  if (op->kind == SK_SJLT)
+  if (op->kind == SK_SJLT) {
     SK_REQUIRE(op->alpha >= 1 && op->alpha <= 32, SK_EINVAL, "alpha must be in 1..32 (got %d)", op->alpha);
+    SK_REQUIRE(op->construction == SK_SJLT_BLOCK || op->construction == SK_SJLT_GRAPH, SK_EINVAL,
+               "unknown SJLT construction %d", op->construction);
+  } else {
+    SK_REQUIRE(op->construction == 0, SK_EINVAL, "construction applies to the SJLT operator only");
+  }
   if (op->kind == SK_SRHT)
     SK_REQUIRE(is_pow2(op_rows(in)), SK_EUNSUPPORTED, "SRHT needs n a power of two (got %lld)",
                (long long)op_rows(in));
@@ -339,47 +454,23 @@ int sketch_apply(sk_ctx* ctx, const sk_input* in, const sk_op_desc* op, int32_t 
   if (int rc = validate_out(in, out, out && out->St)) return rc;
   SK_HIP(hipSetDevice(ctx->c.device));
 
-  sk_handle* H = new (std::nothrow) sk_handle;
-  SK_REQUIRE(H, SK_ENOMEM, "host allocation failed");
-  Handle* h = &H->h;
-  h->ctx = &ctx->c;
-  h->kind = op->kind;
-  h->alpha = op->kind == SK_SJLT ? op->alpha : 1;
-  h->prec = op->prec;
-  h->dtype = in->dtype;
-  h->input = in->input;
-  h->n = op_rows(in);
-  h->seed = seed;
   hipStream_t st = (hipStream_t)stream;
-  if (h->kind == SK_SJLT) {
-    if (in->input == SK_DENSE) {
-      sjlt_pick_chunks(h->dtype, d, h->alpha, out && out->St, &h->kc, &h->kct);
-    } else {
-      h->kc = sjlt_chunk_for(d, h->alpha, 4);
-      h->kct = 0;
-    }
+  int kc = 64, kct = 0;
+  if (op->kind == SK_SJLT) {
+    if (in->input == SK_DENSE) sjlt_pick_chunks(in->dtype, d, op->alpha, out && out->St, &kc, &kct);
+    else kc = sjlt_chunk_for(d, op->alpha, 4);
   }
+  sk_handle* H = nullptr;
+  if (int rc = new_handle(&ctx->c, op->kind, op->alpha, op->construction, op->prec, in->dtype, in->input,
+                          op_rows(in), seed, kc, kct, &H))
+    return rc;
+  Handle* h = &H->h;
   int rc = validate_width(h, d);
-  if (!rc && h->kind == SK_SRHT) rc = dev_alloc(&h->srht_D, (size_t)h->n);
-  if (!rc && h->kind == SK_SRHT) rc = dev_alloc(&h->srht_Db, (size_t)((h->n + 255) / 256 * 8));
-  if (!rc && h->kind == SK_SRHT) {
-    if (h->dtype == SK_F64) rc = dev_alloc((double**)&h->srht_Dv, (size_t)h->n);
-    else rc = dev_alloc((float**)&h->srht_Dv, (size_t)h->n);
-  }
   if (!rc) rc = add_block(h, d);
   if (!rc) rc = gen_blocks(h, 0, 1, st);
   if (!rc) rc = compute_blocks(h, in, 0, 1, out, st);
   if (rc) {
-    const std::string msg = g_err;
-    (void)hipStreamSynchronize(st);
-    for (auto& b : h->blocks) free_block(b);
-    if (h->srht_D) (void)hipFree(h->srht_D);
-    if (h->srht_Dv) (void)hipFree(h->srht_Dv);
-    if (h->srht_Db) (void)hipFree(h->srht_Db);
-    if (h->srht_mu) (void)hipFree(h->srht_mu);
-    h->magic = 0;
-    delete H;
-    g_err = msg;
+    discard_handle(H, st);
     return rc;
   }
   ctx->c.live_handles++;
@@ -396,13 +487,21 @@ int sketch_extend(sk_handle* H, const sk_input* in, int32_t dd, int32_t nblocks,
   SK_REQUIRE(nblocks >= 1 && nblocks <= 64, SK_EINVAL, "nblocks must be in 1..64");
   if (int rc = validate_width(h, dd)) return rc;
   if (int rc = validate_out(in, out_new, out_new && out_new->St)) return rc;
+  SK_REQUIRE((int64_t)h->d + (int64_t)dd * nblocks <= 0x7fffffffLL, SK_EINVAL, "total width above 2^31-1");
   SK_HIP(hipSetDevice(h->ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const int b0 = (int)h->blocks.size();
-  for (int i = 0; i < nblocks; ++i)
-    if (int rc = add_block(h, dd)) return rc;
-  if (int rc = gen_blocks(h, b0, b0 + nblocks, st)) return rc;
-  return compute_blocks(h, in, b0, b0 + nblocks, out_new, st);
+  const int32_t d0 = h->d;
+  int rc = SK_OK;
+  for (int i = 0; i < nblocks && !rc; ++i) rc = add_block(h, dd);
+  if (!rc) rc = gen_blocks(h, b0, b0 + nblocks, st);
+  if (!rc) rc = compute_blocks(h, in, b0, b0 + nblocks, out_new, st);
+  if (rc) {
+    const std::string msg = g_err;
+    drop_blocks(h, b0, d0, st);
+    g_err = msg;
+  }
+  return rc;
 }
 
 int sketch_rerun(sk_handle* H, const sk_input* in, uint64_t seed, const sk_output* out, void* stream) {
@@ -477,7 +576,17 @@ int sketch_get_rows(const sk_handle* H, int64_t i0, int64_t i1, int64_t j0, int6
     const Block& B = h->blocks[b];
     const int jj = (int)(j - B.col0);
     double* o = out + (j - j0) * ldo;
-    if (h->kind == SK_SJLT) {
+    if (h->kind == SK_SJLT && h->construction == SK_SJLT_GRAPH) {
+      const double s = 1.0 / sqrt((double)h->alpha);
+      uint32_t codes[32];
+      for (int64_t i = i0; i < i1; ++i) {
+        sjlt_graph_codes(key, (uint32_t)B.index, (uint32_t)i, h->alpha, (uint32_t)B.w, codes);
+        double v = 0.0;
+        for (int c = 0; c < h->alpha; ++c)
+          if ((int)(codes[c] >> 1) == jj) v = (codes[c] & 1u) ? -s : s;
+        o[i - i0] = v;
+      }
+    } else if (h->kind == SK_SJLT) {
       const uint32_t wc = (uint32_t)(B.w / h->alpha);
       const uint32_t c = (uint32_t)jj / wc;
       const double s = 1.0 / sqrt((double)h->alpha);
@@ -534,6 +643,134 @@ int sketch_get_gaussian(const sk_handle* H, int32_t block, uint16_t* bits) {
   SK_HIP(hipDeviceSynchronize());
   SK_HIP(hipMemcpy(bits, h->blocks[block].gbf, sizeof(uint16_t) * h->n * h->blocks[block].w,
                    hipMemcpyDeviceToHost));
+  return SK_OK;
+}
+
+int sketch_test_hook(sk_ctx* ctx, int32_t hook, int64_t arg) {
+  if (int rc = check_ctx(ctx)) return rc;
+  if (hook == SK_HOOK_FAIL_ALLOC) {
+    SK_REQUIRE(arg >= 0, SK_EINVAL, "allocation countdown must be >= 0");
+    ctx->c.fail_alloc = arg;
+  } else if (hook == SK_HOOK_FAIL_GRAPH) {
+    ctx->c.fail_graph = arg != 0;
+  } else {
+    SK_REQUIRE(false, SK_EINVAL, "unknown test hook %d", hook);
+  }
+  return SK_OK;
+}
+
+int sketch_test_poison_lds(sk_ctx* ctx, uint32_t pattern, void* stream) {
+  if (int rc = check_ctx(ctx)) return rc;
+  SK_HIP(hipSetDevice(ctx->c.device));
+  static bool attr_set = false;
+  if (!attr_set) {
+    SK_HIP(hipFuncSetAttribute((const void*)poison_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               160 * 1024));
+    attr_set = true;
+  }
+  poison_lds_kernel<<<4 * ctx->c.num_cu, 1024, 160 * 1024, (hipStream_t)stream>>>(pattern);
+  SK_HIP(hipGetLastError());
+  return SK_OK;
+}
+
+// ---- operator state: the handle's operator is a pure function of these fields
+// (Algorithm 1's JL-Operator(d, n) per block, drawn from the seed), so the
+// state is a few hundred bytes and import regenerates every block's metadata.
+namespace {
+constexpr uint32_t STATE_MAGIC = 0x54534b53u;  // "SKST"
+constexpr uint32_t STATE_VERSION = 1;
+struct StateHead {
+  uint32_t magic, version;
+  int32_t kind, alpha, construction, prec, dtype, input;
+  int64_t n;
+  uint64_t seed;
+  int32_t kc, kct, nblocks, d;
+};
+static_assert(sizeof(StateHead) == 64, "state header layout: the block widths follow at byte 64");
+uint64_t fnv1a(const unsigned char* p, size_t len) {
+  uint64_t x = 0xcbf29ce484222325ull;
+  for (size_t i = 0; i < len; ++i) x = (x ^ p[i]) * 0x100000001b3ull;
+  return x;
+}
+}  // namespace
+
+int sketch_state_export(const sk_handle* H, void* buf, size_t* len) {
+  if (int rc = check_handle(H)) return rc;
+  SK_REQUIRE(len, SK_EINVAL, "len is NULL");
+  const Handle* h = &H->h;
+  const size_t need = sizeof(StateHead) + sizeof(int32_t) * h->blocks.size() + sizeof(uint64_t);
+  if (!buf) {
+    *len = need;
+    return SK_OK;
+  }
+  SK_REQUIRE(*len >= need, SK_EINVAL, "buffer of %zu bytes, %zu needed", *len, need);
+  StateHead hd;
+  memset(&hd, 0, sizeof(hd));
+  hd.magic = STATE_MAGIC;
+  hd.version = STATE_VERSION;
+  hd.kind = h->kind;
+  hd.alpha = h->alpha;
+  hd.construction = h->construction;
+  hd.prec = h->prec;
+  hd.dtype = h->dtype;
+  hd.input = h->input;
+  hd.n = h->n;
+  hd.seed = h->seed;
+  hd.kc = h->kc;
+  hd.kct = h->kct;
+  hd.nblocks = (int32_t)h->blocks.size();
+  hd.d = h->d;
+  unsigned char* p = (unsigned char*)buf;
+  memcpy(p, &hd, sizeof(hd));
+  for (size_t b = 0; b < h->blocks.size(); ++b)
+    memcpy(p + sizeof(hd) + sizeof(int32_t) * b, &h->blocks[b].w, sizeof(int32_t));
+  const uint64_t sum = fnv1a(p, need - sizeof(uint64_t));
+  memcpy(p + need - sizeof(uint64_t), &sum, sizeof(sum));
+  *len = need;
+  return SK_OK;
+}
+
+int sketch_state_import(sk_ctx* ctx, const void* buf, size_t len, sk_handle** out) {
+  if (int rc = check_ctx(ctx)) return rc;
+  SK_REQUIRE(buf && out, SK_EINVAL, "NULL argument");
+  *out = nullptr;
+  SK_REQUIRE(len >= sizeof(StateHead) + sizeof(uint64_t), SK_EINVAL, "state too short (%zu bytes)", len);
+  StateHead hd;
+  memcpy(&hd, buf, sizeof(hd));
+  SK_REQUIRE(hd.magic == STATE_MAGIC, SK_EINVAL, "not a sketch operator state");
+  SK_REQUIRE(hd.version == STATE_VERSION, SK_EINVAL, "state version %u, expected %u", hd.version, STATE_VERSION);
+  SK_REQUIRE(hd.nblocks >= 1 && hd.nblocks <= (1 << 20), SK_EINVAL, "state holds %d blocks", hd.nblocks);
+  const size_t need = sizeof(StateHead) + sizeof(int32_t) * (size_t)hd.nblocks + sizeof(uint64_t);
+  SK_REQUIRE(len == need, SK_EINVAL, "state of %zu bytes, %zu expected for %d blocks", len, need, hd.nblocks);
+  const unsigned char* p = (const unsigned char*)buf;
+  uint64_t sum;
+  memcpy(&sum, p + need - sizeof(uint64_t), sizeof(sum));
+  SK_REQUIRE(sum == fnv1a(p, need - sizeof(uint64_t)), SK_EINVAL, "state checksum mismatch (corrupted)");
+  SK_REQUIRE(hd.kind >= SK_GAUSSIAN && hd.kind <= SK_SRHT, SK_EINVAL, "state: unknown kind %d", hd.kind);
+  SK_REQUIRE(hd.input == SK_DENSE || hd.input == SK_POINTS, SK_EINVAL, "state: unknown input kind");
+  SK_REQUIRE(hd.dtype == SK_F64 || hd.dtype == SK_F32, SK_EINVAL, "state: unknown dtype");
+  SK_REQUIRE(hd.prec >= SK_PREC_NATIVE && hd.prec <= SK_PREC_BF16X3, SK_EINVAL, "state: unknown precision");
+  SK_REQUIRE(hd.n >= 1 && hd.n <= 0x7fffffffLL, SK_EINVAL, "state: n out of range");
+  if (hd.kind == SK_SJLT) {
+    SK_REQUIRE(hd.alpha >= 1 && hd.alpha <= 32, SK_EINVAL, "state: alpha out of range");
+    SK_REQUIRE(hd.construction == SK_SJLT_BLOCK || hd.construction == SK_SJLT_GRAPH, SK_EINVAL,
+               "state: unknown construction");
+    SK_REQUIRE(hd.kc == 64 || hd.kc == 128 || hd.kc == 256, SK_EINVAL, "state: chunk %d", hd.kc);
+    SK_REQUIRE(hd.kct == 0 || hd.kct == 64 || hd.kct == 128 || hd.kct == 256, SK_EINVAL, "state: chunk %d", hd.kct);
+  }
+  if (hd.kind == SK_SRHT) SK_REQUIRE(is_pow2(hd.n), SK_EUNSUPPORTED, "state: SRHT needs n a power of two");
+  std::vector<int32_t> widths((size_t)hd.nblocks);
+  memcpy(widths.data(), p + sizeof(hd), sizeof(int32_t) * widths.size());
+  int64_t d = 0;
+  for (int32_t w : widths) d += w;
+  SK_REQUIRE(d == hd.d, SK_EINVAL, "state: block widths sum to %lld, not %d", (long long)d, hd.d);
+  SK_HIP(hipSetDevice(ctx->c.device));
+  // metadata generated on the null stream, then waited for: the call returns a
+  // handle whose device data is complete
+  if (int rc = make_operator_handle(&ctx->c, hd.kind, hd.alpha, hd.construction, hd.prec, hd.dtype, hd.input, hd.n,
+                                    hd.seed, hd.kc, hd.kct, widths.data(), hd.nblocks, out, nullptr))
+    return rc;
+  SK_HIP(hipStreamSynchronize(nullptr));
   return SK_OK;
 }
 

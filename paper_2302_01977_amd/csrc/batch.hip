@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(NW * 64)
     }
     sjlt_tile<T, TRANS, NW, NJ, RPL, KCK, LDSE>((const T*)it.A, it.lda, it.L, it.K, l0, 0, it.nT, active,
                                                 it.ptr + jb, (int64_t)it.w + 1, it.ent, 0, eptr[0], eptr[1],
-                                                it.kcap, it.ms, (T*)it.out + (int64_t)jb * it.ldo, it.ldo,
+                                                it.kcap, it.kcap, it.ms, (T*)it.out + (int64_t)jb * it.ldo, it.ldo,
                                                 (T)it.scale);
     __syncthreads();  // the next item reuses the LDS
   }
@@ -179,6 +179,7 @@ struct BatchRound {
   std::vector<int> meta_matrix;  // matrix of each meta item
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  bool eager = false;  // graph capture failed: the round runs launch by launch
 };
 
 struct Batch {
@@ -212,9 +213,9 @@ static void free_batch_buffers(Batch* b) {
 }
 
 template <typename P>
-static int upload(P** dst, const std::vector<P>& v, hipStream_t st) {
+static int upload(Ctx* c, P** dst, const std::vector<P>& v, hipStream_t st) {
   if (v.empty()) return SK_OK;
-  SK_HIP(hipMalloc((void**)dst, sizeof(P) * v.size()));
+  if (int rc = ctx_malloc(c, (void**)dst, sizeof(P) * v.size())) return rc;
   SK_HIP(hipMemcpyAsync(*dst, v.data(), sizeof(P) * v.size(), hipMemcpyHostToDevice, st));
   return SK_OK;
 }
@@ -244,7 +245,7 @@ static int build_rounds(Batch* b, const BatchCfg& c, int max_rounds, hipStream_t
       off_ent.push_back(total);
       total += align256(sizeof(int32_t) * nT * b->kcap);
     }
-  SK_HIP(hipMalloc((void**)&b->meta_buf, std::max<size_t>(total, 256)));
+  if (int rc = ctx_malloc(b->ctx, (void**)&b->meta_buf, std::max<size_t>(total, 256))) return rc;
   const Key dummy{0, 0};
   (void)dummy;
   const int TL = 64 * c.rpl;
@@ -306,9 +307,9 @@ static int build_rounds(Batch* b, const BatchCfg& c, int max_rounds, hipStream_t
     }
     R.nmeta = (int)R.h_meta.size();
     R.nchunks = (int)chunks.size();
-    if (int rc = upload(&R.d_meta, R.h_meta, st)) return rc;
-    if (int rc = upload(&R.d_chunks, chunks, st)) return rc;
-    if (int rc = upload(&R.d_items, items, st)) return rc;
+    if (int rc = upload(b->ctx, &R.d_meta, R.h_meta, st)) return rc;
+    if (int rc = upload(b->ctx, &R.d_chunks, chunks, st)) return rc;
+    if (int rc = upload(b->ctx, &R.d_items, items, st)) return rc;
     for (int tr = 0; tr < 2; ++tr) {
       // largest tiles (most sources) first; ties in item order
       std::stable_sort(work[tr].begin(), work[tr].end(),
@@ -318,7 +319,7 @@ static int build_rounds(Batch* b, const BatchCfg& c, int max_rounds, hipStream_t
       std::vector<int2> wl;
       for (auto& w : work[tr]) wl.push_back(w.second);
       R.nwork[tr] = (int)wl.size();
-      if (int rc = upload(&R.d_work[tr], wl, st)) return rc;
+      if (int rc = upload(b->ctx, &R.d_work[tr], wl, st)) return rc;
     }
     SK_HIP(hipStreamSynchronize(st));  // the host vectors above go out of scope
   }
@@ -342,23 +343,44 @@ static int round_kernels(Batch* b, BatchRound& R, hipStream_t st) {
   return SK_OK;
 }
 
+// Capture round R into a graph on the private stream.  Returns SK_OK with
+// R.gexec set, or an error code; on error nothing of the capture is left.
+static int capture_round(Batch* b, BatchRound& R) {
+  if (!b->cap) SK_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  SK_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+  const int rc = round_kernels(b, R, b->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->cap, &g);
+  if (rc || e != hipSuccess || b->ctx->fail_graph) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    set_error("graph capture failed (injected by the graph-failure test hook)");
+    return SK_EHIP;
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return hip_fail(ei, "hipGraphInstantiate");
+  }
+  R.graph = g;
+  R.gexec = x;
+  return SK_OK;
+}
+
 static int run_round(Batch* b, int r, hipStream_t st) {
   BatchRound& R = b->rounds[r];
   ProfScope ps(b->ctx, "sjlt_batch", st);
-  if (!(b->flags & SK_BATCH_GRAPH)) return round_kernels(b, R, st);
-  if (!R.gexec) {
-    if (!b->cap) SK_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
-    SK_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
-    const int rc = round_kernels(b, R, b->cap);
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(b->cap, &g);
-    if (rc) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
-    }
-    SK_HIP(e);
-    R.graph = g;
-    SK_HIP(hipGraphInstantiate(&R.gexec, R.graph, nullptr, nullptr, 0));
+  if (!(b->flags & SK_BATCH_GRAPH) || R.eager) return round_kernels(b, R, st);
+  if (!R.gexec && capture_round(b, R) != SK_OK) {
+    // a round that cannot be captured (the runtime refuses the capture or the
+    // instantiation) runs launch by launch from now on: same kernels, same
+    // arguments, so the results do not change
+    R.eager = true;
+    return round_kernels(b, R, st);
   }
   SK_HIP(hipGraphLaunch(R.gexec, st));
   return SK_OK;
@@ -539,6 +561,18 @@ int sketch_batch_info(const sk_batch* B, int32_t* nrounds, int32_t* shape) {
   return SK_OK;
 }
 
+int sketch_batch_mode(const sk_batch* B, int32_t round, int32_t* mode) {
+  SK_REQUIRE(B && B->b.magic == 0x534b4254u, SK_ESTATE, "invalid or destroyed batch");
+  const Batch* b = &B->b;
+  SK_REQUIRE(round >= 0 && round < (int)b->rounds.size() && mode, SK_EINVAL, "round out of range or mode NULL");
+  const BatchRound& R = b->rounds[round];
+  *mode = !(b->flags & SK_BATCH_GRAPH) ? SK_ROUND_EAGER
+          : R.eager                    ? SK_ROUND_CAPTURE_FAILED
+          : R.gexec                    ? SK_ROUND_GRAPH
+                                       : SK_ROUND_NOT_CAPTURED;
+  return SK_OK;
+}
+
 int sketch_batch_destroy(sk_batch* B) {
   SK_REQUIRE(B && B->b.magic == 0x534b4254u, SK_ESTATE, "invalid or destroyed batch");
   Batch* b = &B->b;
@@ -550,6 +584,47 @@ int sketch_batch_destroy(sk_batch* B) {
   b->magic = 0;
   delete B;
   return SK_OK;
+}
+
+int sketch_apply_batched(sk_ctx* ctx, const sk_input* ins, const sk_op_desc* op, const int32_t* d, int32_t dd,
+                         const uint64_t* seeds, const sk_output* outs, int32_t count, int32_t flags, sk_handle** hs,
+                         void* stream) {
+  SK_REQUIRE(ctx && ctx->c.magic == CTX_MAGIC, SK_ESTATE, "invalid or released context");
+  SK_REQUIRE(op, SK_EINVAL, "operator description is NULL");
+  SK_REQUIRE(op->kind == SK_SJLT && op->construction == SK_SJLT_BLOCK, SK_EUNSUPPORTED,
+             "the batched sketch uses the SJLT operator with the block construction");
+  SK_REQUIRE(op->flags == 0, SK_EINVAL, "flags of the operator description must be 0");
+  SK_REQUIRE((flags & ~(SK_BATCH_GRAPH | SK_BATCH_AUTOTUNE)) == 0, SK_EINVAL, "unknown batch flags 0x%x", flags);
+  if (hs)
+    for (int i = 0; i < count; ++i) hs[i] = nullptr;
+  sk_batch* B = nullptr;
+  if (int rc = sketch_batch_create(ctx, ins, count, d, dd, op->alpha, seeds, outs, flags, &B, stream)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = sketch_batch_run(B, 0, (int)B->b.rounds.size(), stream);
+  // per-matrix handles hold the same operators (blocks of width dd drawn from
+  // seeds[i]) with their own bucket tables, as apply(dd) + extend(dd) would
+  for (int i = 0; hs && !rc && i < count; ++i) {
+    const int nb = d[i] / dd;
+    std::vector<int32_t> widths((size_t)nb, dd);
+    int kc = 64, kct = 0;
+    sjlt_pick_chunks(ins[i].dtype, dd, op->alpha, outs[i].St != nullptr, &kc, &kct);
+    rc = make_operator_handle(&ctx->c, SK_SJLT, op->alpha, SK_SJLT_BLOCK, SK_PREC_NATIVE, ins[i].dtype, SK_DENSE,
+                              ins[i].n, seeds[i], kc, kct, widths.data(), nb, &hs[i], st);
+  }
+  const std::string msg = rc ? std::string(sketch_last_error()) : std::string();
+  const int rc2 = sketch_batch_destroy(B);  // synchronises the device
+  if (rc && hs) {
+    for (int i = 0; i < count; ++i)
+      if (hs[i]) {
+        (void)sketch_release(hs[i]);
+        hs[i] = nullptr;
+      }
+  }
+  if (rc) {
+    set_error("%s", msg.c_str());
+    return rc;
+  }
+  return rc2;
 }
 
 }  // extern "C"

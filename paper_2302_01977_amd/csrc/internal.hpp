@@ -17,6 +17,7 @@ constexpr uint32_t HND_MAGIC = 0x534b4844u;  // "SKHD"
 constexpr int KC_MAX = 256;   // largest chunk of sources of the SJLT bucket tables
 constexpr int MAX_PASS_BLOCKS = 16;
 constexpr int MAX_PASS_GROUPS = 64;
+constexpr int MAX_PASS_COLS = 1024;  // columns of one pass (MAX_PASS_GROUPS groups of 16)
 
 void set_error(const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
@@ -69,7 +70,15 @@ struct Ctx {
   std::vector<hipEvent_t> pool;
   // autotuner results: shape key -> tuned parameters
   std::map<std::string, std::vector<int>> tune;
+  // test hooks (sketch_test_hook): the fail_alloc-th device allocation from
+  // now on fails (0: off); graph capture reports failure
+  int64_t fail_alloc = 0;
+  bool fail_graph = false;
 };
+
+// Every device allocation made for a context goes through here (the allocation
+// failure hook counts them).  SK_ENOMEM with a message on failure.
+int ctx_malloc(Ctx* c, void** p, size_t bytes);
 
 // Brackets one kernel launch with HIP events on its stream when profiling is on.
 struct ProfScope {
@@ -85,6 +94,7 @@ struct Handle {
   uint32_t magic = HND_MAGIC;
   Ctx* ctx = nullptr;
   int32_t kind = 0, alpha = 1, prec = 0, dtype = 0, input = 0;
+  int32_t construction = 0;  // SJLT: SK_SJLT_BLOCK or SK_SJLT_GRAPH
   int64_t n = 0;  // rows of R
   int32_t kc = 64;  // SJLT: sources per chunk of the bucket tables
   int32_t kct = 0;  // SJLT: chunk of the S' tables when it differs from kc (0: S' uses the S tables)
@@ -172,6 +182,9 @@ int launch_sjlt_dma_t(Ctx* c, int dtype, int nw, int nj, int kc, const void* A, 
 size_t dma_t_lds_bytes(int esz, int kc, int nblk, int kcap);
 
 int ensure_work(Ctx* c, size_t bytes);
+int make_operator_handle(Ctx* c, int kind, int alpha, int construction, int prec, int dtype, int input, int64_t n,
+                         uint64_t seed, int kc, int kct, const int32_t* widths, int nb, sk_handle** out,
+                         hipStream_t st);
 int sjlt_chunk_for(int w, int alpha, int lam);
 // chunk sizes of a new dense SJLT operator of width d: for S, and for S'
 void sjlt_pick_chunks(int dtype, int d, int alpha, bool want_t, int* kc, int* kct);

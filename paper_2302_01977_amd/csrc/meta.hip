@@ -30,11 +30,22 @@ struct MetaLds {
 
 // Hash of source k0 + kk (one thread per source): for every chunk c of the
 // block an offset in [0, w/alpha) and a sign, as code = (column << 1) | negative.
+// With GRAPH the alpha columns of a source are the graph construction's
+// distinct draws over the whole block (width w = wc * alpha is not required:
+// wc carries w itself).
+template <bool GRAPH>
 __device__ __forceinline__ void hash_chunk(MetaLds& L, uint32_t* __restrict__ codes, bool write_codes, int64_t k0,
                                            int nk, int alpha, uint32_t wc, uint32_t block, Key key) {
   const int kk = threadIdx.x;
   if (kk >= nk) return;
   const int64_t k = k0 + kk;
+  if constexpr (GRAPH) {
+    uint32_t* sc = &L.sc[kk * alpha];
+    sjlt_graph_codes(key, block, (uint32_t)k, alpha, wc, sc);
+    if (write_codes)
+      for (int c = 0; c < alpha; ++c) codes[k * alpha + c] = sc[c];
+    return;
+  }
   const uint32_t sbits = philox(2u, block, (uint32_t)k, 0u, key.k0, key.k1).v[0];
   for (int c4 = 0; c4 < alpha; c4 += 4) {
     const U4 o = philox(1u, block, (uint32_t)k, (uint32_t)(c4 >> 2), key.k0, key.k1);
@@ -57,6 +68,13 @@ __device__ __forceinline__ void hash_chunk(MetaLds& L, uint32_t* __restrict__ co
 // lanes); the earlier waves contribute their per-column counts.  Column starts
 // come from a workgroup-wide exclusive scan.  Requires blockDim.x == KC_MAX and
 // w <= 1024; the caller's writes of L.sc are ordered by the first barrier.
+//
+// GRAPH: a column may come from any c (the columns of one source are distinct,
+// so a lane holds a column at most once).  One round per distinct column among
+// the wave's entries matches it against all alpha codes of every lane: the
+// lanes holding it form one mask M, and a lane's rank is the number of lanes
+// of M below it.
+template <bool GRAPH>
 __device__ __forceinline__ void bucket_chunk(MetaLds& L, int nk, int alpha, int w, int kc, int kcap, int t,
                                              int32_t* __restrict__ ptr, int32_t* __restrict__ ent) {
   const int kk = threadIdx.x, lane = kk & 63, wv = kk >> 6;
@@ -65,6 +83,29 @@ __device__ __forceinline__ void bucket_chunk(MetaLds& L, int nk, int alpha, int 
   __syncthreads();
   const bool act = kk < nk;
   const uint64_t below = (1ull << lane) - 1ull;
+  if constexpr (GRAPH) {
+    // bits of this lane's codes not yet ranked (codes hold (col << 1) | neg in
+    // their low 16 bits; ranks go to bits 16.. as they are found)
+    uint32_t pend = act ? (alpha >= 32 ? 0xFFFFFFFFu : (1u << alpha) - 1u) : 0u;
+    for (;;) {
+      const uint64_t any = __ballot(pend != 0u);
+      if (!any) break;
+      const int lead = __builtin_ctzll(any);
+      const int c0 = pend ? __builtin_ctz(pend) : 0;
+      const uint32_t mine = act ? (L.sc[kk * alpha + c0] & 0xFFFFu) >> 1 : 0u;
+      const uint32_t lc = __builtin_amdgcn_readlane(mine, lead);  // this round's column
+      int hit = -1;
+      if (act)
+        for (int c = 0; c < alpha; ++c)
+          if (((L.sc[kk * alpha + c] & 0xFFFFu) >> 1) == lc) hit = c;
+      const uint64_t M = __ballot(hit >= 0);
+      if (hit >= 0) {
+        L.sc[kk * alpha + hit] |= (uint32_t)__popcll(M & below) << 16;
+        pend &= ~(1u << hit);
+      }
+      if (lane == lead) L.wh[wv * w + lc] = __popcll(M);
+    }
+  } else {
   for (int c = 0; c < alpha; ++c) {
     const uint32_t col = act ? (L.sc[kk * alpha + c] >> 1) : 0xFFFFFFFFu;
     uint64_t todo = __ballot(act);
@@ -78,6 +119,7 @@ __device__ __forceinline__ void bucket_chunk(MetaLds& L, int nk, int alpha, int 
       todo &= ~same;
     }
     if (act) L.sc[kk * alpha + c] |= r << 16;
+  }
   }
   __syncthreads();
   // per column: the counts of the earlier waves (in place) and the chunk's count
@@ -134,8 +176,9 @@ __global__ void __launch_bounds__(KC_MAX) sjlt_meta_batch(const MetaItem* __rest
   const MetaItem& m = items[l.x];
   const int64_t k0 = (int64_t)l.y * m.kc;
   const int nk = (int)min((int64_t)m.kc, m.n - k0);
-  hash_chunk(L, m.codes, true, k0, nk, m.alpha, (uint32_t)(m.w / m.alpha), (uint32_t)m.block, Key{m.k0, m.k1});
-  bucket_chunk(L, nk, m.alpha, m.w, m.kc, m.kcap, l.y, m.ptr, m.ent);
+  hash_chunk<false>(L, m.codes, true, k0, nk, m.alpha, (uint32_t)(m.w / m.alpha), (uint32_t)m.block,
+                    Key{m.k0, m.k1});
+  bucket_chunk<false>(L, nk, m.alpha, m.w, m.kc, m.kcap, l.y, m.ptr, m.ent);
 }
 
 int launch_sjlt_meta_batch(const MetaItem* items, const int2* chunks, int nchunks, hipStream_t st) {
@@ -163,6 +206,7 @@ struct MetaBlocks {
   int32_t nb;
 };
 
+template <bool GRAPH>
 __global__ void __launch_bounds__(KC_MAX) sjlt_meta_fused(MetaBlocks mb, int64_t n, int alpha, Key key) {
   __shared__ MetaLds L;
   int b = 0;
@@ -174,8 +218,9 @@ __global__ void __launch_bounds__(KC_MAX) sjlt_meta_fused(MetaBlocks mb, int64_t
   const int w = mb.w[b];
   const int64_t k0 = (int64_t)t * m.kc;
   const int nk = (int)min((int64_t)m.kc, n - k0);
-  hash_chunk(L, mb.codes[b], s0, k0, nk, alpha, (uint32_t)(w / alpha), mb.index[b], key);
-  bucket_chunk(L, nk, alpha, w, m.kc, m.kcap, t, m.ptr, m.ent);
+  hash_chunk<GRAPH>(L, mb.codes[b], s0, k0, nk, alpha, GRAPH ? (uint32_t)w : (uint32_t)(w / alpha), mb.index[b],
+                    key);
+  bucket_chunk<GRAPH>(L, nk, alpha, w, m.kc, m.kcap, t, m.ptr, m.ent);
 }
 
 int launch_sjlt_meta(Handle* h, int b0, int b1, hipStream_t st) {
@@ -200,7 +245,10 @@ int launch_sjlt_meta(Handle* h, int b0, int b1, hipStream_t st) {
     }
     mb.first[mb.nb] = grid;
     ProfScope ps(h->ctx, "sjlt_meta", st);
-    sjlt_meta_fused<<<grid, KC_MAX, 0, st>>>(mb, n, h->alpha, key_of(h->seed));
+    if (h->construction == SK_SJLT_GRAPH)
+      sjlt_meta_fused<true><<<grid, KC_MAX, 0, st>>>(mb, n, h->alpha, key_of(h->seed));
+    else
+      sjlt_meta_fused<false><<<grid, KC_MAX, 0, st>>>(mb, n, h->alpha, key_of(h->seed));
     SK_HIP(hipGetLastError());
   }
   return SK_OK;

@@ -36,6 +36,15 @@ __global__ void __launch_bounds__(NW * 64)
   extern __shared__ __attribute__((aligned(16))) char smem[];
   float* const tile = (float*)smem;
   uint32_t* const ents = (uint32_t*)(smem + (KCK + 1) * 64 * 4);
+  // null entries (zero row, +1.0f) in the 8 slots past the staged regions,
+  // which the straight-line slots of the last bucket may read
+  if constexpr (LDSE) {
+    if (threadIdx.x < 8) {
+      const int q = pass.nblk * pass.kcap + (int)threadIdx.x;
+      ents[q * 2] = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char*)smem + (uint32_t)(KCK * 256);
+      ents[q * 2 + 1] = 0x3f800000u;
+    }
+  }
   constexpr int NTHR = NW * 64;
   const uint32_t tile_lds = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char*)smem;
   const int tid = threadIdx.x;

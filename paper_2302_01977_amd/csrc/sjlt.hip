@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(NW * 64)
   T* dst = split > 1 ? part + (int64_t)s * L * ((int64_t)pass.ngroups * NJ) + jc * L : out + jc * ldo;
   sjlt_tile<T, TRANS, NW, NJ, RPL, KCK, LDSE>(A, lda, L, K, l0, t0, t1, active, pass.ptr[blk] + jb,
                                               (int64_t)pass.wtot[blk] + 1, pass.ent[blk], blk, eptr[0], eptr[1],
-                                              pass.kcap, pass.ms, dst, split > 1 ? L : ldo,
+                                              pass.kcap, pass.nblk * pass.kcap, pass.ms, dst, split > 1 ? L : ldo,
                                               split > 1 ? T(1) : scale);
 }
 

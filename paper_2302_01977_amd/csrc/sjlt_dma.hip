@@ -68,6 +68,19 @@ __global__ void __launch_bounds__(NW * 64)
     ((T*)smem)[KCK * TL + e] = T(0);
     ((T*)(smem + TBYTES))[KCK * TL + e] = T(0);
   }
+  // null entries (zero row, +1) in the 8 slots past each entry buffer, which
+  // the straight-line slots of the last bucket may read: the FP32 form
+  // multiplies by the staged sign
+  if (tid < 16) {
+    const int b = tid >> 3, q = pass.nblk * pass.kcap + (tid & 7);
+    const uint32_t zrow = tile_base(b) + (uint32_t)(KCK * TL * SZ);
+    if constexpr (PACK) {
+      ents_of(b)[q] = zrow;
+    } else {
+      ents_of(b)[q * 2] = zrow;
+      ents_of(b)[q * 2 + 1] = 0x3f800000u;
+    }
+  }
 
   auto load_meta = [&](int t) {
 #pragma unroll

@@ -77,8 +77,8 @@ template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK, bool LDSE>
 __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, int64_t L, int64_t K, int64_t l0,
                                           int t0, int t1, bool active, const int32_t* __restrict__ ptr,
                                           int64_t prow, const int32_t* __restrict__ ent, int blk,
-                                          const uint32_t* eptr0, const uint32_t* eptr1, int kcap, int ms,
-                                          T* __restrict__ dst, int64_t ldd, T sc) {
+                                          const uint32_t* eptr0, const uint32_t* eptr1, int kcap, int epad,
+                                          int ms, T* __restrict__ dst, int64_t ldd, T sc) {
   constexpr int SZ = sizeof(T);
   constexpr int VECN = 16 / SZ;  // elements per 16-byte vector
   constexpr int TL = 64 * RPL;   // lanes (rows of A, or columns of A for S') per workgroup
@@ -113,6 +113,21 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
   u32x4 ebuf[2] = {u32x4{0u, 0u, 0u, 0u}, u32x4{0u, 0u, 0u, 0u}};
   uint32_t bnd = 0, bndN = 0, bnd_nx = 0, bndN_nx = 0;
   for (int e = tid; e < TL; e += NTHR) tile[KCK * TL + e] = T(0);
+  // The straight-line slots of the last bucket may read up to 7 entries past
+  // the staged regions (entries epad..epad+7).  Those slots address the zero
+  // row, but the FP32 form also multiplies by the staged sign, so they hold a
+  // null entry (zero row, +1) instead of whatever the LDS held before.
+  if constexpr (LDSE) {
+    if (tid < 8) {
+      const uint32_t zrow = tile_lds + (uint32_t)(KCK * TL * SZ);
+      if constexpr (PACK) {
+        ents[epad + tid] = zrow;
+      } else {
+        ents[(epad + tid) * 2] = zrow;
+        ents[(epad + tid) * 2 + 1] = 0x3f800000u;
+      }
+    }
+  }
   // ---------------------------------------------------------------- staging
   u32x4 buf[NV];
   // Per-thread geometry of the staged tile.  NTHR * VECN is a multiple of TL

@@ -10,6 +10,8 @@
 //                                          mu = mulhi32(word, nu)
 //   Gaussian g_{k,j}, global column j    : (5, j, k, 0), words 0 and 1, Box-Muller
 //                                          in FP64, rounded to bfloat16 (RNE).
+//   SJLT graph draw, row k, step c, blk b: (6, b, k, c >> 2), word c & 3,
+//                                          t_c = mulhi32(word, w_b - alpha + c + 1)
 // Compiled for host and device so that the library's host queries
 // (sketch_get_rows) and its kernels evaluate the same definition.
 #pragma once
@@ -67,6 +69,24 @@ SK_HD uint32_t sjlt_code(Key key, uint32_t block, uint32_t k, uint32_t c, uint32
   const uint32_t off = mulhi(o.v[c & 3], wc);
   const U4 s = philox(2u, block, k, 0u, key.k0, key.k1);
   return ((c * wc + off) << 1) | ((s.v[0] >> c) & 1u);
+}
+
+// SJLT (graph construction, section 2.4.3): the alpha distinct columns of row
+// k of a block of width w, as codes (col << 1) | negative in code[0..alpha).
+// A uniformly random alpha-subset by Floyd's sampling: step c draws t uniform
+// in [0, j], j = w - alpha + c, and takes t unless an earlier step took it,
+// else j.  The signs use the block construction's counter (2, b, k, 0), bit c.
+SK_HD void sjlt_graph_codes(Key key, uint32_t block, uint32_t k, int alpha, uint32_t w, uint32_t* code) {
+  const uint32_t sbits = philox(2u, block, k, 0u, key.k0, key.k1).v[0];
+  U4 o = philox(6u, block, k, 0u, key.k0, key.k1);
+  for (int c = 0; c < alpha; ++c) {
+    if (c > 0 && (c & 3) == 0) o = philox(6u, block, k, (uint32_t)(c >> 2), key.k0, key.k1);
+    const uint32_t j = w - (uint32_t)alpha + (uint32_t)c;
+    uint32_t t = mulhi(o.v[c & 3], j + 1u);
+    for (int q = 0; q < c; ++q)
+      if ((code[q] >> 1) == t) t = j;  // j itself is never taken before step c
+    code[c] = (t << 1) | ((sbits >> c) & 1u);
+  }
 }
 
 SK_HD int srht_neg(Key key, uint32_t k) {

@@ -49,7 +49,11 @@ def test_state_errors_without_gpu():
     assert lib.sketch_width(None, None, None) == abi.SK_ESTATE
     assert lib.sketch_finalize(None) == abi.SK_ESTATE
     assert lib.sketch_get_rows(None, 0, 1, 0, 1, None, 1) == abi.SK_ESTATE
-    assert lib.sketch_init(None, 0) == abi.SK_EINVAL
+    assert lib.sketch_init(None, 0, 0) == abi.SK_EINVAL
+    assert lib.sketch_state_export(None, None, None) == abi.SK_ESTATE
+    assert lib.sketch_state_import(None, None, 0, None) == abi.SK_ESTATE
+    assert lib.sketch_test_hook(None, abi.SK_HOOK_FAIL_ALLOC, 1) == abi.SK_ESTATE
+    assert lib.sketch_batch_mode(None, 0, None) == abi.SK_ESTATE
     h = ctypes.c_void_p()
     assert lib.sketch_apply(None, None, None, 16, 1, None, ctypes.byref(h), None) == abi.SK_ESTATE
 
@@ -60,7 +64,7 @@ def test_init_fails_cleanly_without_device():
         pytest.skip("a GPU is present")
     abi, lib = _lib()
     ctx = ctypes.c_void_p()
-    rc = lib.sketch_init(ctypes.byref(ctx), 0)
+    rc = lib.sketch_init(ctypes.byref(ctx), 0, 0)
     assert rc in (abi.SK_EHIP, abi.SK_EINVAL)
     assert not ctx.value
     assert len(lib.sketch_last_error()) > 0
