@@ -205,15 +205,18 @@ class Sketch:
         _check(self._lib.sketch_extend(self.h, ctypes.byref(self._in), dd, nblocks,
                                        ctypes.byref(_output(Sn, Stn)), _stream(stream)))
         self.widths += [dd] * nblocks
-        self.S = Sn if self.S is None else _hcat(self.S, Sn)
-        if self.transpose:
-            self.St = Stn if self.St is None else _hcat(self.St, Stn)
+        # a handle resumed from a state (or made by the batched call) has no
+        # columns computed yet: S / St stay None until rerun computes all of them
+        if self.S is not None:
+            self.S = _hcat(self.S, Sn)
+            if self.transpose:
+                self.St = _hcat(self.St, Stn)
         return Sn, Stn
 
     def rerun(self, seed, stream=None):
         """Redraw every block from ``seed`` and recompute all columns in place."""
-        if self.S is None:
-            d = sum(self.widths)
+        d = int(sum(self.widths))
+        if self.S is None or self.S.shape[1] != d:   # every column of the operator is written
             self.S = colmajor(self.rows, d, self.dtype, self.device)
             self.St = colmajor(self._in.n, d, self.dtype, self.device) if self.transpose else None
         _check(self._lib.sketch_rerun(self.h, ctypes.byref(self._in), seed,
