@@ -144,6 +144,20 @@ int sketch_extend(sk_handle *h, const sk_input *in, int32_t dd, int32_t nblocks,
  * handle exists.  out holds all d columns.  Asynchronous. */
 int sketch_rerun(sk_handle *h, const sk_input *in, uint64_t seed, const sk_output *out, void *stream);
 
+/* sketch_rerun_static: sketch_rerun for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and results as sketch_rerun, bit for bit;
+ * it allocates and frees nothing (no hipMalloc, hipFree or allocating library
+ * routine; launch timing is not recorded).  The kernels' scratch (partial sums
+ * of a split source range) lives in a fixed device array of 64 MiB that the
+ * library holds on every GPU it runs on until the process ends.  A call whose
+ * scratch would exceed 64 MiB fails with SK_EINVAL and a message giving both
+ * sizes; the handle then keeps its previous operator (its metadata is
+ * regenerated on `stream`).  Every call on one GPU shares that GPU's array and
+ * it keeps the last call's contents: calls that overlap on one GPU, from any
+ * context or stream, race; order them on one stream.  Asynchronous. */
+int sketch_rerun_static(sk_handle *h, const sk_input *in, uint64_t seed, const sk_output *out, void *stream);
+
 /* sketch_adjoint: backward of the sketch for the operator blocks
  * [block0, block0 + nblocks) (their columns, in order, are the columns of dS).
  *   DENSE (SJLT): dA = dS R^T (the adjoint of A -> A R), m x n, overwritten;

@@ -45,6 +45,7 @@ _SIGS = {
     "sketch_apply": (c_i32, [c_vp, P(SkInput), P(SkOpDesc), c_i32, c_u64, P(SkOutput), P(c_vp), c_vp]),
     "sketch_extend": (c_i32, [c_vp, P(SkInput), c_i32, c_i32, P(SkOutput), c_vp]),
     "sketch_rerun": (c_i32, [c_vp, P(SkInput), c_u64, P(SkOutput), c_vp]),
+    "sketch_rerun_static": (c_i32, [c_vp, P(SkInput), c_u64, P(SkOutput), c_vp]),
     "sketch_adjoint": (c_i32, [c_vp, P(SkInput), c_i32, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "sketch_width": (c_i32, [c_vp, P(c_i32), P(c_i32)]),
     "sketch_release": (c_i32, [c_vp]),

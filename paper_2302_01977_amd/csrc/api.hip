@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "internal.hpp"
@@ -39,7 +40,7 @@ static hipEvent_t pool_event(Ctx* c) {
 }
 
 ProfScope::ProfScope(Ctx* c_, const char* n_, hipStream_t s_) : c(c_), name(n_), st(s_) {
-  if (!c->prof) return;
+  if (!c->prof || c->use_fixed) return;  // (event creation may allocate)
   a = pool_event(c);
   if (a) (void)hipEventRecord(a, st);
 }
@@ -71,6 +72,12 @@ int ctx_malloc(Ctx* c, void** p, size_t bytes) {
 }
 
 int ensure_work(Ctx* c, size_t bytes) {
+  if (c->use_fixed) {
+    SK_REQUIRE(bytes <= c->fixed_bytes, SK_EINVAL,
+               "this call needs %zu bytes of scratch; the allocation-free entry point has %zu (use sketch_rerun)",
+               bytes, c->fixed_bytes);
+    return SK_OK;
+  }
   if (bytes <= c->work_bytes) return SK_OK;
   if (c->work) {
     SK_HIP(hipFree(c->work));  // implicit device synchronisation: no kernel still reads it
@@ -343,6 +350,30 @@ static int check_same_input(const Handle* h, const sk_input* in) {
   return SK_OK;
 }
 
+// Scratch of the allocation-free entry point: a fixed array in device memory,
+// one copy per GPU the library runs on, held until the process ends.  Host code
+// never uses its name as an address: sketch_init looks up each device's copy
+// with hipGetSymbolAddress and the kernels receive that pointer.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[STATIC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[256];  // per device: address of its copy of `scratch`
+
+// Address of this device's copy of the scratch array (the device is current).
+static int static_scratch(int device, void** out) {
+  SK_REQUIRE(device >= 0 && device < 256, SK_EINVAL, "device index %d out of range", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+    g_scratch_dev[device] = p;
+  }
+  *out = g_scratch_dev[device];
+  return SK_OK;
+}
+
 // Fills the whole 160 KB LDS allocation of each workgroup with `pattern`
 // (test hook: later kernels on the same CUs start with those bits in LDS).
 __global__ void __launch_bounds__(1024) poison_lds_kernel(uint32_t pattern) {
@@ -373,6 +404,12 @@ int sketch_init(sk_ctx** ctx, int32_t device, uint32_t flags) {
   c->c.device = device;
   c->c.num_cu = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
   c->c.prof = (flags & SK_INIT_PROFILE) != 0;
+  if (int rc = static_scratch(device, &c->c.fixed_work)) {
+    c->c.magic = 0;
+    delete c;
+    return rc;
+  }
+  c->c.fixed_bytes = STATIC_SCRATCH_BYTES;
   *ctx = c;
   return SK_OK;
 }
@@ -515,6 +552,32 @@ int sketch_rerun(sk_handle* H, const sk_input* in, uint64_t seed, const sk_outpu
   h->seed = seed;
   if (int rc = gen_blocks(h, 0, (int)h->blocks.size(), st)) return rc;
   return compute_blocks(h, in, 0, (int)h->blocks.size(), out, st);
+}
+
+int sketch_rerun_static(sk_handle* H, const sk_input* in, uint64_t seed, const sk_output* out, void* stream) {
+  if (int rc = check_handle(H)) return rc;
+  Handle* h = &H->h;
+  if (int rc = validate_input(in)) return rc;
+  if (int rc = check_same_input(h, in)) return rc;
+  if (int rc = validate_out(in, out, out && out->St)) return rc;
+  Ctx* c = h->ctx;
+  SK_REQUIRE(c->fixed_work, SK_ESTATE, "the context has no scratch array");
+  SK_HIP(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t seed0 = h->seed;
+  const int nb = (int)h->blocks.size();
+  c->use_fixed = true;
+  h->seed = seed;
+  int rc = gen_blocks(h, 0, nb, st);
+  if (!rc) rc = compute_blocks(h, in, 0, nb, out, st);
+  if (rc) {  // the handle keeps its previous operator
+    const std::string msg = g_err;
+    h->seed = seed0;
+    (void)gen_blocks(h, 0, nb, st);
+    g_err = msg;
+  }
+  c->use_fixed = false;
+  return rc;
 }
 
 int sketch_adjoint(sk_handle* H, const sk_input* in, int32_t block0, int32_t nblocks, const void* dS, int64_t lddS,

@@ -508,7 +508,7 @@ static int run_f64(Ctx* c, const TA* A, int64_t lda, int64_t m, int64_t n, const
   if (split > 1) {
     const int rc = ensure_work(c, (size_t)split * (size_t)m * (size_t)W * sizeof(TS));
     if (rc) return rc;
-    part = (TS*)c->work;
+    part = (TS*)work_ptr(c);
   }
   dim3 grid((unsigned)((m + 63) / 64), (unsigned)split, (unsigned)gz);
   {
@@ -551,7 +551,7 @@ static int run_bf16(Ctx* c, bool x3, const float* A, int64_t lda, int64_t m, int
   if (split > 1) {
     const int rc = ensure_work(c, (size_t)split * (size_t)m * (size_t)W * sizeof(float));
     if (rc) return rc;
-    part = (float*)c->work;
+    part = (float*)work_ptr(c);
   }
   // XCD-major order: 8 / split XCDs per source slice, row tiles dealt over them
   const int per = 8 / split;

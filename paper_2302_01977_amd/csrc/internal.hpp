@@ -74,7 +74,16 @@ struct Ctx {
   // now on fails (0: off); graph capture reports failure
   int64_t fail_alloc = 0;
   bool fail_graph = false;
+  // allocation-free calls: while use_fixed is set, kernels take their scratch
+  // from the library's fixed per-device array (fixed_work, fixed_bytes) and
+  // ensure_work never allocates
+  void* fixed_work = nullptr;
+  size_t fixed_bytes = 0;
+  bool use_fixed = false;
 };
+
+// the workspace the kernels write (valid after a successful ensure_work)
+inline void* work_ptr(const Ctx* c) { return c->use_fixed ? c->fixed_work : c->work; }
 
 // Every device allocation made for a context goes through here (the allocation
 // failure hook counts them).  SK_ENOMEM with a message on failure.

@@ -472,7 +472,7 @@ int launch_mf_pass(Handle* h, const sk_input* in, int b0, int b1, void* out, int
   float* part = nullptr;
   if (split > 1) {
     if (int rc = ensure_work(h->ctx, (size_t)split * (size_t)N * (size_t)W * 4)) return rc;
-    part = (float*)h->ctx->work;
+    part = (float*)work_ptr(h->ctx);
   }
   const float c2 = (float)(LOG2E / (2.0 * (double)in->h * (double)in->h));
   const float scale = (float)(1.0 / sqrt((double)h->alpha));
@@ -535,8 +535,8 @@ int launch_mf_backward(Handle* h, const sk_input* in, int b0, int b1, const floa
   // workspace: row-major copy of W, then per-workgroup dh partials
   const size_t wrm_bytes = ((size_t)N * Wt * 4 + 255) & ~(size_t)255;
   if (int rc = ensure_work(h->ctx, wrm_bytes + (size_t)nwg * 8)) return rc;
-  float* Wrm = (float*)h->ctx->work;
-  double* dh_part = (double*)((char*)h->ctx->work + wrm_bytes);
+  float* Wrm = (float*)work_ptr(h->ctx);
+  double* dh_part = (double*)((char*)work_ptr(h->ctx) + wrm_bytes);
   {
     dim3 grid((unsigned)((N + 31) / 32), (unsigned)((Wt + 31) / 32));
     transpose_kernel<<<grid, 256, 0, st>>>(Wd, ldw, N, Wt, Wrm);

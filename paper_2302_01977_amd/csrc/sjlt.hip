@@ -331,7 +331,7 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
   if (split > 1) {
     const int rc = ensure_work(h->ctx, (size_t)split * (size_t)L * (size_t)W * esz);
     if (rc) return rc;
-    part = h->ctx->work;
+    part = work_ptr(h->ctx);
   }
   const double scale = 1.0 / sqrt((double)h->alpha);
   Ctx* c = h->ctx;
@@ -366,7 +366,7 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
       void* dpart = nullptr;
       if (dsplit > 1) {
         if ((rc = ensure_work(c, (size_t)dsplit * (size_t)L * (size_t)W * esz))) return rc;
-        dpart = c->work;
+        dpart = work_ptr(c);
       }
       rc = trans ? launch_sjlt_dma_t(c, h->dtype, ds.nw, ds.nj, kc, in->A, in->lda, L, K, dp, out, ldo, scale,
                                      dsplit, dpart, st)
@@ -388,7 +388,7 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
         }
         return SK_OK;
       }
-      if (split > 1) part = c->work;  // the workspace may have grown above
+      if (split > 1) part = work_ptr(c);  // the workspace may have grown above
     }
   }
   if (h->dtype == SK_F64) {

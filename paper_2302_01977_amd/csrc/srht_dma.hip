@@ -324,7 +324,7 @@ static int run_srht_dma(Ctx* c, const T* A, int64_t lda, int64_t L, int64_t K, c
   if (split > 1) {
     const int rc = ensure_work(c, (size_t)split * (size_t)L * (size_t)W * sizeof(T));
     if (rc) return rc;
-    part = (T*)c->work;
+    part = (T*)work_ptr(c);
   }
   const size_t shmem = TRANS ? 2 * (size_t)64 * (KCK + 8) * sizeof(T) : 2 * (size_t)KCK * 64 * sizeof(T);
   auto kern = TRANS ? srht_dma_t_kernel<T, NW, NJ, KCK> : srht_dma_kernel<T, NW, NJ, KCK>;
