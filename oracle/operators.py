@@ -178,18 +178,28 @@ def popcount(x):
     return cnt
 
 
+def srht_nu(n):
+    """nu = 2^ceil(log2 n): the Hadamard dimension of section 7.2 (nu = n when n
+    is a power of two)."""
+    nu = 1
+    while nu < n:
+        nu *= 2
+    return nu
+
+
 def srht_block(n, w, col0, seed):
     """Dense FP64 SRHT block from the element formula of section 7.2:
 
-        R[k, jj] = D_k * (-1)^{popcount(k & mu_{col0 + jj})} / sqrt(w)
+        R[k, jj] = D_k * (-1)^{popcount(k & mu_{col0 + jj})} / sqrt(w),   k < n,
 
-    with nu = n (the build supports n a power of two).  Indices are 0-based, so
-    the Hadamard entry (-1)^{i . j} uses the bits of the 0-based i and j.
+    with nu = 2^ceil(log2 n) and mu uniform over [nu].  For n not a power of two
+    this is D~ H_nu P with the padded diagonal D~ = [D 0] of eq. (DtildeH): only
+    the first n rows of H_nu are ever used.  Indices are 0-based, so the
+    Hadamard entry (-1)^{i . j} uses the bits of the 0-based i and j.
     """
-    if not is_pow2(n):
-        raise ValueError("SRHT requires n to be a power of two")
+    nu = srht_nu(n)
     D = srht_diag(n, seed)
-    mu = srht_samples(n, col0, col0 + w, seed)
+    mu = srht_samples(nu, col0, col0 + w, seed)
     k = np.arange(n, dtype=np.uint64)[:, None]
     par = popcount(k & mu.astype(np.uint64)[None, :]) & 1
     return D[:, None] * (1.0 - 2.0 * par) / math.sqrt(w)

@@ -52,6 +52,56 @@ def sketch_columns(A, kind, n, widths, seed, cols, alpha=4, transpose=False, blo
     return out
 
 
+def fwht_rows(X):
+    """Unnormalised natural-order Walsh-Hadamard transform of every row of X
+    (row length a power of two), by the Sylvester recursion
+    [a b] H_2m = [a H_m + b H_m, a H_m - b H_m]."""
+    X = np.asarray(X, dtype=np.float64)
+    nu = X.shape[1]
+    if nu == 1:
+        return X.copy()
+    h = nu // 2
+    a, b = fwht_rows(X[:, :h]), fwht_rows(X[:, h:])
+    return np.concatenate([a + b, a - b], axis=1)
+
+
+def hadamard_split(A):
+    """A H_nu for A with n columns, nu = 2^ceil(log2 n), A padded with zero
+    columns, by the split of section 7.1: with k = 2^floor(log2 n), n = k + r,
+    p = 2^ceil(log2 r) and q = k / p,
+
+        A H_2k = [A_k H_k + A^ H_p [I ... I],  A_k H_k - A^ H_p [I ... I]]
+
+    (eqs. (had1) and (hadiden)), A_k the first k columns and A^ the last r
+    padded to p.  Two transforms of dimensions k and p replace the one of
+    dimension 2k.  For n a power of two it is the plain transform."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    k = 1
+    while 2 * k <= n:
+        k *= 2
+    r = n - k
+    if r == 0:
+        return fwht_rows(A)
+    p = 1
+    while p < r:
+        p *= 2
+    q = k // p
+    Ak = fwht_rows(A[:, :k])
+    Ahat = np.zeros((m, p))
+    Ahat[:, :r] = A[:, k:]
+    T = np.tile(fwht_rows(Ahat), (1, q))        # A^ H_p [I ... I]
+    return np.concatenate([Ak + T, Ak - T], axis=1)
+
+
+def srht_sketch_fast(A, D, mu, w):
+    """S = A D H_nu P / sqrt(w) by the transform of section 7.1 (any n): the
+    rows of A D are transformed with ``hadamard_split`` and the sampled columns
+    mu are kept."""
+    AD = np.asarray(A, dtype=np.float64) * np.asarray(D, dtype=np.float64)[None, :]
+    return hadamard_split(AD)[:, np.asarray(mu)] / np.sqrt(w)
+
+
 def adjoint(dS, R):
     """dA = dS R^T: the adjoint of A -> A R applied to dS (FP64)."""
     return np.asarray(dS, dtype=np.float64) @ np.asarray(R, dtype=np.float64).T

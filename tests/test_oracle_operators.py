@@ -135,9 +135,27 @@ def test_srht_rows_unit_norm_and_samples_uniform():
     assert ((cnt - exp) ** 2 / exp).sum() < 16 + 6 * math.sqrt(32)
 
 
-def test_srht_rejects_non_power_of_two():
-    with pytest.raises(ValueError):
-        ops.srht_block(100, 8, 0, 1)
+@pytest.mark.parametrize("n", [100, 129, 1000, 3])
+def test_srht_any_n_is_padded_DHP(n):
+    """Section 7.2, eq. (DtildeH): for n not a power of two, R = D~ H_nu P with
+    nu = 2^ceil(log2 n) and D~ = [D 0]; the element formula gives exactly the
+    first n rows of that explicit product, with unit row norms."""
+    w, col0, seed = 24, 8, 5
+    nu = ops.srht_nu(n)
+    assert nu >= n > nu // 2
+    D = ops.srht_diag(n, seed)
+    mu = ops.srht_samples(nu, col0, col0 + w, seed)
+    assert mu.max() < nu
+    Dt = np.zeros((n, nu))
+    Dt[np.arange(n), np.arange(n)] = D
+    P = np.zeros((nu, w))
+    P[mu, np.arange(w)] = math.sqrt(nu / w)
+    R = Dt @ (ops.hadamard(nu) / math.sqrt(nu)) @ P
+    Rb = ops.srht_block(n, w, col0, seed)
+    assert np.allclose(Rb, R, rtol=0, atol=1e-14)
+    assert np.allclose((Rb * Rb).sum(1), 1.0, atol=1e-14)
+    # for a power of two the operator is unchanged: nu = n
+    assert ops.srht_nu(128) == 128
 
 
 # ----------------------------------------------------------------- Gaussian

@@ -205,3 +205,37 @@ def test_kernel_row_helpers_match_full_forms_and_differences():
         K = np.exp(-(diff ** 2).sum(1) / (2 * h * h))
         one_sided[t] = -((2 * (R @ W[i]) * K)[:, None] * diff).sum(0) / (h * h)
     assert rel_fro(one_sided, gr) > 1e-2
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 12, 33, 64, 100, 257])
+def test_hadamard_split_is_the_padded_transform(n):
+    """Section 7.1, eqs. (had1) and (hadiden): the k-point / p-point split equals
+    [A 0] H_nu (A padded with zero columns to nu = 2^ceil(log2 n)) as a matrix
+    identity, checked against the explicit Sylvester matrix; for n a power of
+    two it is the plain transform."""
+    A = _rand(7, n, 30 + n)
+    nu = ops.srht_nu(n)
+    Apad = np.zeros((7, nu))
+    Apad[:, :n] = A
+    assert rel_fro(osk.hadamard_split(A), Apad @ ops.hadamard(nu)) < 1e-14
+    # the two halves of the split: A_k H_k +- A^ H_p [I ... I]
+    if n & (n - 1):
+        k = nu // 2
+        assert rel_fro(osk.hadamard_split(A)[:, :k] - osk.hadamard_split(A)[:, k:],
+                       2 * osk.hadamard_split(np.concatenate([np.zeros((7, k)), A[:, k:]], 1))[:, :k]) < 1e-13
+
+
+@pytest.mark.parametrize("m,n,w,col0", [(9, 100, 16, 0), (20, 1000, 40, 24), (5, 3, 8, 8), (33, 129, 64, 0)])
+def test_srht_any_n_fast_path_matches_explicit(m, n, w, col0):
+    """S = A D H P for n not a power of two: the section 7.1 transform path equals
+    the explicit operator of section 7.2 times A (and S' likewise on A^T)."""
+    A = _rand(m, n, 3)
+    D = ops.srht_diag(n, 17)
+    mu = ops.srht_samples(ops.srht_nu(n), col0, col0 + w, 17)
+    R = ops.srht_block(n, w, col0, 17)
+    assert rel_fro(osk.srht_sketch_fast(A, D, mu, w), osk.sketch(A, R)) < 1e-13
+    B = _rand(n, m, 4)
+    assert rel_fro(osk.srht_sketch_fast(B.T, D, mu, w), osk.sketch_t(B, R)) < 1e-13
+    # A = I: the sketch is R itself
+    assert rel_fro(osk.srht_sketch_fast(np.eye(n), D, mu, w), R) < 1e-14
+
