@@ -43,7 +43,7 @@ extern "C" {
 /* status codes */
 #define SK_OK 0
 #define SK_EINVAL (-1)       /* bad argument: NULL pointer, ld < rows, width <= 0, alpha does not divide a width, ... */
-#define SK_EUNSUPPORTED (-2) /* valid request this build does not implement (e.g. SRHT with n not a power of two) */
+#define SK_EUNSUPPORTED (-2) /* valid request this build does not implement (e.g. the batched call with an SRHT operator) */
 #define SK_ENOMEM (-3)       /* device or host allocation failed */
 #define SK_EHIP (-4)         /* a HIP runtime call failed; the message carries hipGetErrorString */
 #define SK_ESTATE (-5)       /* released, foreign or corrupted handle/context */
@@ -51,7 +51,8 @@ extern "C" {
 /* operator kinds (section 2.4) */
 #define SK_GAUSSIAN 0 /* i.i.d. N(0, 1/w_b) entries (values on the bfloat16 grid) */
 #define SK_SJLT 1     /* block construction: alpha chunks of w_b/alpha columns, one +-1/sqrt(alpha) per chunk and row */
-#define SK_SRHT 2     /* R = D H P / sqrt(w_b)-scaled; D Rademacher, H Sylvester-Hadamard (natural order), P uniform samples */
+#define SK_SRHT 2     /* R = D H P / sqrt(w_b)-scaled; D Rademacher, H Sylvester-Hadamard (natural order) of dimension
+                         nu = 2^ceil(log2 n) restricted to its first n rows, P uniform samples of [nu] */
 
 /* element types of A and of the sketches */
 #define SK_F64 0
@@ -126,7 +127,7 @@ const char *sketch_last_error(void);
  * *h receives a new handle owning the operator metadata (release with
  * sketch_release).  d > 0; SJLT with the block construction needs alpha | d, with
  * the graph construction alpha <= d; the SJLT and SRHT kernels need d % 16 == 0;
- * SRHT needs n a power of two.  Asynchronous on `stream`.
+ * SRHT takes any n (H = H_nu, nu = 2^ceil(log2 n), section 7.2).  Asynchronous on `stream`.
  * Errors: SK_EINVAL, SK_EUNSUPPORTED, SK_ENOMEM, SK_EHIP. */
 int sketch_apply(sk_ctx *ctx, const sk_input *in, const sk_op_desc *op, int32_t d, uint64_t seed,
                  const sk_output *out, sk_handle **h, void *stream);

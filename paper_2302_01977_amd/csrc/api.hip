@@ -107,8 +107,6 @@ static void free_block(Block& b) {
   b = Block();
 }
 
-static bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
-
 static int check_ctx(const sk_ctx* c) {
   SK_REQUIRE(c && c->c.magic == CTX_MAGIC, SK_ESTATE, "not a live sketch context");
   return SK_OK;
@@ -480,9 +478,6 @@ int sketch_apply(sk_ctx* ctx, const sk_input* in, const sk_op_desc* op, int32_t 
   } else {
     SK_REQUIRE(op->construction == 0, SK_EINVAL, "construction applies to the SJLT operator only");
   }
-  if (op->kind == SK_SRHT)
-    SK_REQUIRE(is_pow2(op_rows(in)), SK_EUNSUPPORTED, "SRHT needs n a power of two (got %lld)",
-               (long long)op_rows(in));
   if (in->input == SK_POINTS)
     SK_REQUIRE(op->kind == SK_SJLT, SK_EUNSUPPORTED, "the matrix-free kernel sketch uses the SJLT operator");
   SK_REQUIRE(op->prec >= SK_PREC_NATIVE && op->prec <= SK_PREC_BF16X3, SK_EINVAL, "unknown precision %d", op->prec);
@@ -661,7 +656,7 @@ int sketch_get_rows(const sk_handle* H, int64_t i0, int64_t i1, int64_t j0, int6
       const double sw = sqrt((double)B.w);
       for (int64_t i = i0; i < i1; ++i) o[i - i0] = gauss_raw(key, (uint32_t)i, (uint32_t)j) / sw;
     } else {
-      const uint32_t mu = srht_mu(key, (uint32_t)j, (uint32_t)h->n);
+      const uint32_t mu = srht_mu(key, (uint32_t)j, srht_nu(h->n));
       const double s = 1.0 / sqrt((double)B.w);
       for (int64_t i = i0; i < i1; ++i) {
         const int neg = srht_neg(key, (uint32_t)i) ^ (popc32((uint32_t)i & mu) & 1);
@@ -821,7 +816,6 @@ int sketch_state_import(sk_ctx* ctx, const void* buf, size_t len, sk_handle** ou
     SK_REQUIRE(hd.kc == 64 || hd.kc == 128 || hd.kc == 256, SK_EINVAL, "state: chunk %d", hd.kc);
     SK_REQUIRE(hd.kct == 0 || hd.kct == 64 || hd.kct == 128 || hd.kct == 256, SK_EINVAL, "state: chunk %d", hd.kct);
   }
-  if (hd.kind == SK_SRHT) SK_REQUIRE(is_pow2(hd.n), SK_EUNSUPPORTED, "state: SRHT needs n a power of two");
   std::vector<int32_t> widths((size_t)hd.nblocks);
   memcpy(widths.data(), p + sizeof(hd), sizeof(int32_t) * widths.size());
   int64_t d = 0;

@@ -293,7 +293,7 @@ int launch_srht_meta(Handle* h, int64_t j0, int64_t j1, bool draw_D, hipStream_t
     SK_HIP(hipGetLastError());
   }
   if (j1 > j0) {
-    srht_mu_kernel<<<(unsigned)((j1 - j0 + 255) / 256), 256, 0, st>>>(h->srht_mu, j0, j1, (uint32_t)h->n, key);
+    srht_mu_kernel<<<(unsigned)((j1 - j0 + 255) / 256), 256, 0, st>>>(h->srht_mu, j0, j1, srht_nu(h->n), key);
     SK_HIP(hipGetLastError());
   }
   return SK_OK;

@@ -7,7 +7,7 @@
 //   SJLT sign,   row k, chunk c, block b : (2, b, k, 0), word 0, bit c (1 = negative)
 //   SRHT diagonal D_k                    : (3, 0, k, 0), word 0, bit 0 (1 = -1)
 //   SRHT sample mu_j, global column j    : (4, 0, j >> 2, 0), word j & 3,
-//                                          mu = mulhi32(word, nu)
+//                                          mu = mulhi32(word, nu), nu = 2^ceil(log2 n)
 //   Gaussian g_{k,j}, global column j    : (5, j, k, 0), words 0 and 1, Box-Muller
 //                                          in FP64, rounded to bfloat16 (RNE).
 //   SJLT graph draw, row k, step c, blk b: (6, b, k, c >> 2), word c & 3,
@@ -91,6 +91,15 @@ SK_HD void sjlt_graph_codes(Key key, uint32_t block, uint32_t k, int alpha, uint
 
 SK_HD int srht_neg(Key key, uint32_t k) {
   return (int)(philox(3u, 0u, k, 0u, key.k0, key.k1).v[0] & 1u);
+}
+
+// Hadamard dimension of an SRHT on n rows: nu = 2^ceil(log2 n) (section 7.2:
+// for n not a power of two only the first n rows of H_nu are used, D padded
+// with zeros).
+SK_HD uint32_t srht_nu(int64_t n) {
+  uint32_t nu = 1;
+  while ((int64_t)nu < n) nu <<= 1;
+  return nu;
 }
 
 SK_HD uint32_t srht_mu(Key key, uint32_t j, uint32_t nu) {

@@ -1,5 +1,6 @@
-// SRHT sketch of a stored, column-major A with n = nu a power of two
-// (section 7.1: S = A D H P, the cost dominated by the Hadamard transform).
+// SRHT sketch of a stored, column-major A (section 7.1: S = A D H P, the cost
+// dominated by the Hadamard transform), any n: H = H_nu with nu = 2^ceil(log2 n)
+// and A, D padded with zeros past n (section 7.2).
 //
 // Sampled output column j picks Hadamard column mu_j (section 7.2, element
 // formula (H)_{k,mu} = (-1)^{popcount(k & mu)}), so

@@ -28,15 +28,44 @@ def _api():
 
 
 # ------------------------------------------------------------------- SRHT
-@pytest.mark.parametrize("n,w,seed", [(1024, 64, 3), (16, 16, 9), (4096, 256, 12)])
+@pytest.mark.parametrize("n,w,seed", [(1024, 64, 3), (16, 16, 9), (4096, 256, 12), (1000, 64, 4), (3, 16, 5),
+                                      (4097, 32, 6)])
 def test_srht_metadata_bit_exact(ctx, n, w, seed):
+    """D and the samples mu (uniform over [nu], nu = 2^ceil(log2 n)) bit for bit."""
     api = _api()
     A = api.to_device_colmajor(np.ones((2, n)))
     sk = api.Sketch(ctx, A, "srht", w, seed)
     sk.extend(32, nblocks=2)
     D, mu = sk.srht_data(0, w + 64)
     assert np.array_equal(D.astype(np.int64), ops.srht_diag(n, seed))
-    assert np.array_equal(mu.astype(np.int64), ops.srht_samples(n, 0, w + 64, seed))
+    assert np.array_equal(mu.astype(np.int64), ops.srht_samples(ops.srht_nu(n), 0, w + 64, seed))
+    sk.release()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("m,n,ld,w", [(1000, 1000, 1000, 64),     # n = 1000: nu = 1024
+                                      (3008, 3008, 3008, 256),   # a batch-like size: multiple of 64
+                                      (777, 777, 779, 48),       # odd lda: register-staged path
+                                      (64, 5000, 64, 128),       # one row tile: split source range
+                                      (5, 3, 5, 16)])            # fewer rows than one chunk
+def test_srht_any_n_parity(ctx, dtype, m, n, ld, w):
+    """SRHT for n not a power of two (section 7.1 / 7.2: H_nu with nu = 2^ceil(log2 n)
+    and A, D padded with zeros): S (and S' for square A) and an extension against
+    the oracle's explicit operator."""
+    api = _api()
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    A = workloads.random_dense(m, n, 71, dtype)
+    sq = m == n
+    sk = api.Sketch(ctx, _padded_colmajor(A, ld, tdt), "srht", w, 48, transpose=sq)
+    sk.extend(32, nblocks=2)
+    torch.cuda.synchronize()
+    R = ops.operator("srht", n, [w, 32, 32], 48)
+    A64 = A.astype(np.float64)
+    tol = 1e-12 if dtype == np.float64 else 1e-5
+    assert osk.rel_fro(sk.S.cpu().numpy(), A64 @ R) <= tol
+    if sq:
+        assert osk.rel_fro(sk.St.cpu().numpy(), A64.T @ R) <= tol
+    assert np.array_equal(sk.get_rows(0, n, 0, w + 64), R)
     sk.release()
 
 

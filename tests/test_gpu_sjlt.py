@@ -183,9 +183,11 @@ def test_argument_errors(ctx):
     with pytest.raises(api.SketchError) as e:
         api.Sketch(ctx, A, "sjlt", 30, 1, alpha=4)      # alpha does not divide 30
     assert e.value.code == -1
-    with pytest.raises(api.SketchError) as e:
-        api.Sketch(ctx, api.to_device_colmajor(np.ones((8, 12))), "srht", 16, 1)
-    assert e.value.code == -2                          # SRHT needs a power of two
+    # SRHT takes any n (nu = 16 for n = 12)
+    sk = api.Sketch(ctx, api.to_device_colmajor(np.ones((8, 12))), "srht", 16, 1)
+    torch.cuda.synchronize()
+    assert osk.rel_fro(sk.S.cpu().numpy(), np.ones((8, 12)) @ ops.srht_block(12, 16, 0, 1)) <= 1e-12
+    sk.release()
     with pytest.raises(api.SketchError) as e:
         api.Sketch(ctx, A, "sjlt", 24, 1, alpha=4)      # widths are multiples of 16
     assert e.value.code == -1
