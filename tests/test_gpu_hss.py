@@ -88,3 +88,22 @@ def test_nonsymmetric_cauchy_hss_with_gpu_sketches(ctx):
     print("cauchy n=%d: final d %d, max rank %d, error %.2e" % (n, res.final_d, res.max_rank(), err))
     assert res.converged
     assert err <= 1e-7
+
+
+@pytest.mark.parametrize("kind", ["sjlt", "srht"])
+def test_qchem_toeplitz_hss_with_gpu_sketches(ctx, kind):
+    """The paper's QChem Toeplitz matrix (section 8.1, d = 0.1) at n = 1000 (SRHT
+    on a non-power-of-two n): GPU sketches against the oracle's own, compared by
+    final width, ranks and error."""
+    n = 1000
+    A = workloads.qchem_toeplitz_dense(n, 0.1)
+    gs = GPUSketcher(ctx, A, kind, 91, alpha=4, symmetric=True)
+    res = hss.compress(A, 64, gs, d0=64, dd=64, eps_r=1e-6, eps_a=1e-8, symmetric=True)
+    gs.release()
+    os_ = hss.OracleSketcher(A, kind, 91, alpha=4, symmetric=True)
+    ref = hss.compress(A, 64, os_, d0=64, dd=64, eps_r=1e-6, eps_a=1e-8, symmetric=True)
+    err = hss.relative_error(A, res)
+    print("toeplitz %s: final d %d (oracle %d), max rank %d (%d), error %.2e"
+          % (kind, res.final_d, ref.final_d, res.max_rank(), ref.max_rank(), err))
+    assert res.converged and err <= 1e-5
+    assert res.final_d == ref.final_d and abs(res.max_rank() - ref.max_rank()) <= 2

@@ -175,3 +175,18 @@ def test_node_ranks_match_lapack_pivoted_qr_at_level_scaled_tolerance():
         assert len(t.J) == k, (t.lo, t.hi, t.level)
         checked += 1
     assert checked >= 10
+
+
+def test_qchem_toeplitz_hss_meets_tolerance():
+    """The paper's QChem Toeplitz matrix (section 8.1, d = 0.1) compressed by the
+    oracle's adaptive HSS with SJLT sketches: the error meets the tolerance and
+    the ranks stay small (the paper notes they grow slowly with n)."""
+    import workloads as w
+    n = 512
+    A = w.qchem_toeplitz_dense(n, 0.1)
+    sk = hss.OracleSketcher(A, "sjlt", 77, alpha=4, symmetric=True)
+    res = hss.compress(A, 64, sk, d0=64, dd=64, eps_r=1e-6, eps_a=1e-8, symmetric=True)
+    assert res.converged
+    err = hss.relative_error(A, res)
+    assert err <= 10 * 1e-6
+    assert res.max_rank() <= 48

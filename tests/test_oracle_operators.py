@@ -303,3 +303,18 @@ def test_sjlt_graph_jl_statistics():
     var = 2 / w * (nx2 ** 2 - (x ** 4).sum())
     assert abs(vals.mean() - nx2) < 5 * math.sqrt(var / trials)
     assert abs(vals.var() / var - 1) < 0.2
+
+
+def test_qchem_toeplitz_input_matches_the_closed_form():
+    """Section 8.1, QChem Toeplitz: T_ii = pi^2 / (6 d^2), T_ij = (-1)^(i-j) /
+    (d^2 (i-j)^2) with d = 0.1, checked entry by entry on a small n; T is
+    symmetric and Toeplitz."""
+    import workloads
+    n, d = 40, 0.1
+    T = workloads.qchem_toeplitz_dense(n, d)
+    for i in range(n):
+        for j in range(n):
+            ref = math.pi ** 2 / (6 * d * d) if i == j else (-1) ** (i - j) / (d * d * (i - j) ** 2)
+            assert abs(T[i, j] - ref) <= 1e-13 * abs(ref)
+    assert (T == T.T).all()
+    assert (T[1:, 1:] == T[:-1, :-1]).all()

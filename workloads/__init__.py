@@ -187,6 +187,26 @@ def cfg4_matrix(spec, dtype=np.float32):
     return gaussian_kernel_dense(X, spec["h"], 0.0, dtype)
 
 
+def qchem_toeplitz_vector(n, spacing=0.1):
+    """The defining vector of the paper's QChem Toeplitz test matrix (1-D kinetic
+    energy, section 8.1): t[n - 1 + (i - j)] = T_ij with T_ii = pi^2 / (6 d^2) and
+    T_ij = (-1)^(i-j) / (d^2 (i - j)^2) otherwise, d = ``spacing``.  Length 2n - 1,
+    FP64 (symmetric, so t is a palindrome)."""
+    r = np.arange(-(n - 1), n, dtype=np.float64)
+    t = np.empty(2 * n - 1)
+    off = r != 0
+    t[off] = np.where(np.abs(r[off]) % 2 == 1, -1.0, 1.0) / (spacing * spacing * r[off] * r[off])
+    t[~off] = math.pi ** 2 / (6.0 * spacing * spacing)
+    return t
+
+
+def qchem_toeplitz_dense(n, spacing=0.1, dtype=np.float64):
+    """The QChem Toeplitz matrix stored dense, column-major: T_ij = t[n - 1 + i - j]."""
+    t = qchem_toeplitz_vector(n, spacing)
+    i = np.arange(n)
+    return np.asfortranarray(t[n - 1 + i[:, None] - i[None, :]].astype(dtype))
+
+
 def cfg5(N=32768):
     """Matrix-free differentiation: N points uniform in [0,1]^3 (FP32), bandwidth
     h = 0.3, SJLT alpha = 4, d = 256, loss weights W ~ N(0, 1) (N x 256)."""
