@@ -42,10 +42,14 @@ FP64_PEAK_TFLOPS = 78.6
 BF16_PEAK_TFLOPS = 2500.0
 # VALU issue without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
-# the dominant kernel's sources: the traffic figures below are valid only for them
+# the step kernels' sources: the recorded traffic figures are valid only for them
 GATHER_SOURCES = ("paper_2302_01977_amd/csrc/sjlt.hip", "paper_2302_01977_amd/csrc/sjlt_dma.hip",
                   "paper_2302_01977_amd/csrc/sjlt_tile.hpp", "paper_2302_01977_amd/csrc/gather.hpp")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sjlt_gather_cauchy16k_traffic.txt")
+# rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of the step's two kernels (S, S')
+TRAFFIC_FILES = {"sjlt_gather": os.path.join(ROOT, "profiles", "sjlt_gather_S_cauchy16k_traffic.txt"),
+                 "sjlt_gather_t": os.path.join(ROOT, "profiles", "sjlt_gather_St_cauchy16k_traffic.txt")}
+STEP_KERNELS = {"sjlt_gather": "sjlt_gather_kernel<double, false, 16, 16, 1, 256, true> (S = A R)",
+                "sjlt_gather_t": "sjlt_gather_kernel<double, true, 16, 16, 1, 256, true> (S' = A^T R)"}
 
 
 def parse():
@@ -55,10 +59,18 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="cauchy16k", choices=["cauchy16k"])
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--only-main", action="store_true", help="time the SJLT step and the copy reference only")
-    p.add_argument("--only-mf", action="store_true",
-                   help="run the matrix-free leg only and print its figures (for counter profiling)")
-    return p.parse_args()
+    p.add_argument("--leg", default="all",
+                   choices=["all", "main", "srht", "gaussian", "fp32", "mf", "batch", "precision", "hss"],
+                   help="run one leg only and print its figures (for profiling); 'main' = the SJLT step with "
+                        "the copy and read references")
+    p.add_argument("--only-main", action="store_true", help="same as --leg main")
+    p.add_argument("--only-mf", action="store_true", help="same as --leg mf")
+    a = p.parse_args()
+    if a.only_main:
+        a.leg = "main"
+    if a.only_mf:
+        a.leg = "mf"
+    return a
 
 
 def time_steps(fn, steps, warmup):
@@ -103,13 +115,13 @@ def sources_digest():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the S = A R gather kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def recorded_traffic(path):
+    """HBM bytes per launch of a step kernel from its committed rocprofv3
+    counter summary, if it was taken on the current kernel sources."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -164,6 +176,73 @@ def cpu_baseline_extras(A, d, alpha, seed):
                        symmetric=True)
     out["hss_1024_compress"] = {"s": round(time.perf_counter() - t, 4), "final_d": int(res.final_d),
                                 "max_rank": int(res.max_rank()), "converged": bool(res.converged)}
+    return out
+
+
+def cpu_baseline_workloads(A2, seed2):
+    """The oracle on samples of the other workloads, each timed on the host and
+    scaled to the whole workload by its arithmetic (clearly a per-unit
+    extrapolation, not a run of the whole thing):
+      * n = 65536 FP32 kernel matrix, SJLT alpha = 8, d = 512: the 64 sampled
+        columns of S on the first 512 rows, scaled by 65536 / 512 rows and
+        512 / 64 columns;
+      * the 96-matrix batch: S = A_i R_i for 8 of the matrices, scaled by
+        sum n_i^2 d_i over the batch;
+      * the matrix-free forward (N = 32768, d = 256): 1024 rows of S = K R,
+        scaled by N / 1024;
+      * the adaptive HSS compression of the n = 16384 Cauchy matrix (SJLT,
+        eps_r = 1e-8): the whole oracle run."""
+    import numpy as np
+
+    import workloads
+    from oracle import hss
+    from oracle import operators as ops
+    from oracle import sketch as osk
+    out = {}
+    # n = 65536: sampled columns on a row block
+    n3, rows = 65536, 512
+    X = workloads.cfg3_points(n3)
+    d2 = np.zeros((rows, n3))
+    for a in range(3):
+        diff = X[:rows, a][:, None] - X[:, a][None, :]
+        d2 += diff * diff
+    blk = np.exp(-d2 / (2.0 * 0.2 * 0.2))
+    blk[np.arange(rows), np.arange(rows)] += 1e-3
+    blk = blk.astype(np.float32)
+    del d2
+    cols = workloads.sample_columns(512, 64, workloads.DATA_SEED[3])
+    t = time.perf_counter()
+    osk.sketch_columns(blk, "sjlt", n3, [64] * 8, workloads.OP_SEED[3], cols, alpha=8)
+    dt = time.perf_counter() - t
+    out["n65536_sjlt8_d512"] = {"sample": "64 sampled columns of S on rows 0..511", "sample_s": round(dt, 4),
+                                "extrapolated_full_s": round(dt * (n3 / rows) * (512 / 64), 2)}
+    del blk
+    # batch: 8 of the 96 matrices
+    specs = workloads.cfg4_specs()
+    tot = sum(sp["n"] ** 2 * sp["d"] for sp in specs)
+    smp, t_s = 0, 0.0
+    for i, sp in enumerate(specs[:8]):
+        Ai = workloads.cfg4_matrix(sp)
+        t = time.perf_counter()
+        osk.sketch(Ai, ops.operator("sjlt", sp["n"], [64] * (sp["d"] // 64), workloads.OP_SEED[4] + i, alpha=4))
+        t_s += time.perf_counter() - t
+        smp += sp["n"] ** 2 * sp["d"]
+    out["batch96"] = {"sample": "S = A_i R_i for 8 of the 96 matrices", "sample_s": round(t_s, 4),
+                      "extrapolated_full_s": round(t_s * tot / smp, 3)}
+    # matrix-free forward
+    c5 = workloads.cfg5()
+    R5 = ops.sjlt_block(c5["N"], c5["d"], c5["alpha"], 0, c5["seed"])
+    t = time.perf_counter()
+    osk.kernel_sketch_rows(c5["X"].astype(np.float64), float(np.float32(c5["h"])), R5, np.arange(1024))
+    dt = time.perf_counter() - t
+    out["matrix_free_forward"] = {"sample": "1024 of the 32768 rows of S = K(X, h) R", "sample_s": round(dt, 4),
+                                  "extrapolated_full_s": round(dt * c5["N"] / 1024, 2)}
+    # adaptive HSS of the Cauchy matrix, whole run
+    t = time.perf_counter()
+    sk = hss.OracleSketcher(A2, "sjlt", seed2, alpha=4, symmetric=False)
+    res = hss.compress(A2, 256, sk, d0=64, dd=64, eps_r=1e-8, eps_a=1e-8, symmetric=False)
+    out["cauchy16k_hss_compress"] = {"s": round(time.perf_counter() - t, 3), "final_d": int(res.final_d),
+                                     "max_rank": int(res.max_rank()), "converged": bool(res.converged)}
     return out
 
 
@@ -344,6 +423,30 @@ def precision_leg(api, ctx, reps):
     A64 = A.double()
     del A
     torch.cuda.empty_cache()
+    # the library FP64 GEMM (rocBLAS through torch) on the same values: 8 products
+    # of n x n by n x 64 (R drawn by torch: timing only); the FP64 Gaussian
+    # baseline is the faster of it and the FP64-arithmetic kernel above
+    Rg = torch.randn(n, blk, dtype=torch.float64, device="cuda")
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.mm(A64, Rg)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(nblk):
+        torch.mm(A64, Rg)
+    t1.record()
+    torch.cuda.synchronize()
+    lib_ms = t0.elapsed_time(t1)
+    del Rg
+    out["fp64_gemm_library"] = {"ms": round(lib_ms, 3),
+                                "TFLOPs": round(2.0 * n * n * blk * nblk / (lib_ms * 1e-3) / 1e12, 2)}
+    best = min(base_ms, lib_ms)
+    out["fp64_gaussian_baseline_ms"] = round(best, 3)
+    for key in ("bf16x3", "bf16", "sjlt", "srht"):
+        out[key]["speedup_vs_fp64_gaussian"] = round(best / out[key]["ms"], 2)
+        if "lookahead_3_passes" in out[key]:
+            la = out[key]["lookahead_3_passes"]
+            la["speedup_vs_fp64_gaussian"] = round(best / la["ms"], 2)
     for key, kind in (("sjlt", "sjlt"), ("srht", "srht")):
         _, S64 = build(kind, "native", A64, keep=True)
         _, S32 = build(kind, "native", A64.float(), keep=True)
@@ -409,9 +512,14 @@ def main():
     import workloads
     from paper_2302_01977_amd import api
 
-    if args.only_mf:
+    single = {"mf": ("matrix_free", lambda ctx: matrix_free_leg(api, ctx, args.steps, args.warmup)),
+              "batch": ("batched", lambda ctx: batch_leg(api, ctx, max(3, args.steps // 2), 2)),
+              "precision": ("precision_65536", lambda ctx: precision_leg(api, ctx, 2)),
+              "hss": ("hss_1024", lambda ctx: hss_leg(api, ctx))}
+    if args.leg in single:
+        key, fn = single[args.leg]
         ctx = api.Context(0)
-        print(json.dumps({"matrix_free": matrix_free_leg(api, ctx, args.steps, args.warmup)}))
+        print(json.dumps({key: fn(ctx)}))
         ctx.close()
         return
 
@@ -443,14 +551,21 @@ def main():
     results["read_reference"] = {"bytes_per_launch": A.numel() * 8, "ms": round(read_ms, 4),
                                  "GBps": round(read_gbps, 1), "kernel": "torch.sum over the columns of A"}
 
-    kinds = ["sjlt"] if args.only_main else ["sjlt", "srht", "gaussian"]
+    if args.leg in ("srht", "gaussian"):
+        r, sk = stored_leg(api, ctx, A, args.leg, d, seed, alpha, "native", args.steps, args.warmup, step_bytes(8))
+        if sk is not None:
+            sk.release()
+        print(json.dumps({args.leg: r}))
+        ctx.close()
+        return
+    kinds = ["sjlt"] if args.leg in ("main", "fp32") else ["sjlt", "srht", "gaussian"]
     for kind in kinds:
         r, sk = stored_leg(api, ctx, A, kind, d, seed, alpha, "native", args.steps, args.warmup, step_bytes(8))
         results[kind] = r
         if sk is not None:
             sketches[kind] = sk
 
-    if not args.only_main:
+    if args.leg in ("all", "fp32"):
         # library FP64 GEMM (rocBLAS through torch) on the same shapes, for the
         # "faster of the two" FP64 Gaussian baseline; R drawn by torch (timing only)
         Rt = torch.randn(n, d, dtype=torch.float64, device="cuda")
@@ -498,6 +613,13 @@ def main():
             fp32[key] = r
         del A32, ref
         results["fp32_matrix"] = fp32
+    if args.leg == "fp32":
+        print(json.dumps({"fp32_matrix": results["fp32_matrix"]}))
+        for sk in sketches.values():
+            sk.release()
+        ctx.close()
+        return
+    if args.leg == "all":
         results["matrix_free"] = matrix_free_leg(api, ctx, args.steps, args.warmup)
         results["batched"] = batch_leg(api, ctx, max(3, args.steps // 2), 2)
         results["precision_65536"] = precision_leg(api, ctx, 2)
@@ -507,18 +629,29 @@ def main():
     r = results["sjlt"]
     ms = r["ms_per_step"]
     value = r["GBps"]
-    g = r["kernels"].get("sjlt_gather")
-    roof = None
-    if g:
-        bytes_sketch = n * n * 8 + n * d * 8
+    # roofline of the step's dominant kernel (the longer of S and S'), the
+    # other one beside it; per-launch times from the library's HIP events on
+    # the launch stream
+    bytes_sketch = n * n * 8 + n * d * 8
+    per_kernel = {}
+    for name in STEP_KERNELS:
+        g = r["kernels"].get(name)
+        if not g:
+            continue
         ach = bytes_sketch / (g["avg_ms"] * 1e-3) / 1e9
-        traffic = recorded_traffic()
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "sjlt_gather_kernel<double, false, 16, 16, 1, 256> (S = A R launches)", "bytes_per_launch": bytes_sketch,
-                "avg_launch_ms": g["avg_ms"], "frac_of_measured_copy": round(ach / copy_gbps, 4),
-                "frac_of_measured_read": round(ach / read_gbps, 4),
-                "source_digest": sources_digest()}
+        per_kernel[name] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(TRAFFIC_FILES[name]),
+                            "kernel": STEP_KERNELS[name], "bytes_per_launch": bytes_sketch,
+                            "avg_launch_ms": round(g["avg_ms"], 5), "launches": g["launches"],
+                            "frac_of_measured_copy": round(ach / copy_gbps, 4),
+                            "frac_of_measured_read": round(ach / read_gbps, 4)}
+    roof = None
+    if per_kernel:
+        dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_launch_ms"])
+        roof = dict(per_kernel[dom])
+        roof["dominant"] = dom
+        roof["source_digest"] = sources_digest()
+        roof["other"] = {k: v for k, v in per_kernel.items() if k != dom}
     for sk in sketches.values():
         sk.release()
 
@@ -529,6 +662,8 @@ def main():
                "sample": "full workload (operator + S + S', n=16384, d=256) x %d reps, %.2f s each" % (reps, t_cpu),
                "cpu_model": cpu_model()}
         cpu.update(cpu_baseline_extras(A_host, d, alpha, seed))
+        if args.leg == "all":
+            cpu["other_workloads"] = cpu_baseline_workloads(A_host, seed)
 
     out = {
         "metric": "S=AR effective GB/s & % HBM peak, SJLT/SRHT/bf16x3 vs FP64 Gaussian at 1e-6",

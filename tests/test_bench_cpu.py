@@ -31,10 +31,10 @@ def test_traffic_figure_needs_matching_sources(tmp_path, monkeypatch):
     import bench
     f = tmp_path / "traffic.txt"
     f.write_text("source_digest: %s\nhbm_bytes_per_launch: 123.0\n" % bench.sources_digest())
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    assert bench.recorded_traffic() == 123.0
+    assert bench.recorded_traffic(str(f)) == 123.0
     f.write_text("source_digest: 0000000000000000\nhbm_bytes_per_launch: 123.0\n")
-    assert bench.recorded_traffic() is None
+    assert bench.recorded_traffic(str(f)) is None
+    assert bench.recorded_traffic(str(tmp_path / "missing.txt")) is None
 
 
 def test_cpu_baseline_extras():
