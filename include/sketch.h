@@ -290,6 +290,99 @@ int sketch_apply_batched(sk_ctx *ctx, const sk_input *ins, const sk_op_desc *op,
                          const uint64_t *seeds, const sk_output *outs, int32_t count, int32_t flags, sk_handle **hs,
                          void *stream);
 
+/* ---- per-node HSS work on the device ---------------------------------------
+ * Batched FP64 kernels for the node-level steps of Algorithm 1 (appendix "HSS
+ * Algorithm Detailed Description"): the local sketches S_tau = S(I_tau, iota) -
+ * D_tau R(I_tau, iota) and their internal-node forms (products and row
+ * selections), the QR of the first d columns and the projection of the next dd
+ * columns for the stopping test of section 3 (eq. "stopping_criteria-1"), the
+ * interpolative decomposition by column-pivoted QR, and the local operators
+ * R_tau = U_tau^T R(...).  Each call takes a host array of `count` descriptors,
+ * one per node (sizes may differ), copies it to the device on `stream` (the
+ * call waits for that copy) and enqueues one launch for the batch.  All
+ * matrices are FP64, column-major, in device memory owned by the caller.
+ * Errors: SK_ESTATE (context), SK_EINVAL (a descriptor out of range; its index
+ * is in the message), SK_ENOMEM, SK_EHIP. */
+typedef struct {
+  int32_t m, n, k;        /* C is m x n; op(A) is m x k, op(B) k x n */
+  int32_t transA, transB; /* nonzero: op(X) = X^T */
+  double alpha, beta;     /* C = beta C + alpha op(A) op(B); beta = 0 ignores C's old values */
+  const double *A;
+  int64_t lda;
+  const double *B;
+  int64_t ldb;
+  double *C;
+  int64_t ldc;
+} sk_gemm_desc;
+int sketch_batched_gemm(sk_ctx *ctx, const sk_gemm_desc *descs, int32_t count, void *stream);
+
+/* Householder QR of A (m x n, overwritten: R above the diagonal, reflectors
+ * below); rdiag[j] = |R_jj| for j < r = min(m, n) <= 1024; when Q != NULL the
+ * explicit Q (m x r, ldq >= m) with A = Q R. */
+typedef struct {
+  int32_t m, n;
+  double *A;
+  int64_t lda;
+  double *rdiag;
+  double *Q;
+  int64_t ldq;
+} sk_qr_desc;
+int sketch_batched_qr(sk_ctx *ctx, const sk_qr_desc *descs, int32_t count, void *stream);
+
+/* Interpolative decomposition M ~ M(:, J) Y of M (p x q, overwritten) by
+ * column-pivoted Householder QR: column norms recomputed exactly at each step,
+ * pivot = first column of maximal norm, stop at the first k with norm <
+ * max(eps_a, eps_r |R_00|).  Writes *rank = k (device int), perm[0:q] (J =
+ * perm[0:k]) and Y (k x q, ldy >= min(p, q)) with Y(:, J) = I and the other
+ * columns R11^{-1} R12. */
+typedef struct {
+  int32_t p, q;
+  double *M;
+  int64_t ldm;
+  double eps_r, eps_a;
+  int32_t *perm;
+  int32_t *rank;
+  double *Y;
+  int64_t ldy;
+} sk_id_desc;
+int sketch_batched_id(sk_ctx *ctx, const sk_id_desc *descs, int32_t count, void *stream);
+
+/* *out = ||A||_F for A m x n (device scalar) */
+typedef struct {
+  int32_t m, n;
+  const double *A;
+  int64_t lda;
+  double *out;
+} sk_norm_desc;
+int sketch_batched_norm(sk_ctx *ctx, const sk_norm_desc *descs, int32_t count, void *stream);
+
+/* dst(i, j) = src(r_i, c_j), r_i = rows[i] (or row0 + i when rows is NULL),
+ * c_j = cols[j] (or col0 + j): row selections and submatrices such as
+ * B = A(I~, I~') (dst m x n, ldd >= m; rows / cols device int64 arrays); with
+ * trans != 0 the transpose, dst(i, j) = src(c_j, r_i). */
+typedef struct {
+  int32_t m, n;
+  int32_t trans;
+  const double *src;
+  int64_t lds;
+  const int64_t *rows;
+  const int64_t *cols;
+  int64_t row0, col0;
+  double *dst;
+  int64_t ldd;
+} sk_gather_desc;
+int sketch_batched_gather(sk_ctx *ctx, const sk_gather_desc *descs, int32_t count, void *stream);
+
+/* sketch_get_rows_device: R(i0:i1, j0:j1) in FP64 written to device memory
+ * (out[(i - i0) + (j - j0) * ldo]) from the handle's device metadata (the
+ * leaf corrections D_tau R(I_tau, iota) and local operators of Algorithm 1).
+ * Asynchronous on `stream`; out is caller-owned device memory.
+ * Errors: SK_ESTATE (not a live handle), SK_EINVAL (rows outside [0, n),
+ * columns outside [0, d), out NULL for a non-empty range, ldo < i1 - i0),
+ * SK_EHIP. */
+int sketch_get_rows_device(const sk_handle *h, int64_t i0, int64_t i1, int64_t j0, int64_t j1, double *out,
+                           int64_t ldo, void *stream);
+
 /* ---- operator state (checkpoint / resume) ---------------------------------
  * An operator is a pure function of (kind, alpha, construction, precision,
  * element type, input kind, n, seed, table chunk sizes, block widths): Algorithm

@@ -37,6 +37,34 @@ class SkOutput(ctypes.Structure):
     _fields_ = [("S", c_vp), ("ldS", c_i64), ("St", c_vp), ("ldSt", c_i64)]
 
 
+c_f64 = ctypes.c_double
+
+
+class SkGemmDesc(ctypes.Structure):
+    _fields_ = [("m", c_i32), ("n", c_i32), ("k", c_i32), ("transA", c_i32), ("transB", c_i32),
+                ("alpha", c_f64), ("beta", c_f64), ("A", c_vp), ("lda", c_i64), ("B", c_vp), ("ldb", c_i64),
+                ("C", c_vp), ("ldc", c_i64)]
+
+
+class SkQrDesc(ctypes.Structure):
+    _fields_ = [("m", c_i32), ("n", c_i32), ("A", c_vp), ("lda", c_i64), ("rdiag", c_vp), ("Q", c_vp),
+                ("ldq", c_i64)]
+
+
+class SkIdDesc(ctypes.Structure):
+    _fields_ = [("p", c_i32), ("q", c_i32), ("M", c_vp), ("ldm", c_i64), ("eps_r", c_f64), ("eps_a", c_f64),
+                ("perm", c_vp), ("rank", c_vp), ("Y", c_vp), ("ldy", c_i64)]
+
+
+class SkNormDesc(ctypes.Structure):
+    _fields_ = [("m", c_i32), ("n", c_i32), ("A", c_vp), ("lda", c_i64), ("out", c_vp)]
+
+
+class SkGatherDesc(ctypes.Structure):
+    _fields_ = [("m", c_i32), ("n", c_i32), ("trans", c_i32), ("src", c_vp), ("lds", c_i64), ("rows", c_vp),
+                ("cols", c_vp), ("row0", c_i64), ("col0", c_i64), ("dst", c_vp), ("ldd", c_i64)]
+
+
 P = ctypes.POINTER
 _SIGS = {
     "sketch_init": (c_i32, [P(c_vp), c_i32, ctypes.c_uint32]),
@@ -65,6 +93,12 @@ _SIGS = {
     "sketch_state_export": (c_i32, [c_vp, c_vp, P(ctypes.c_size_t)]),
     "sketch_state_import": (c_i32, [c_vp, c_vp, ctypes.c_size_t, P(c_vp)]),
     "sketch_test_hook": (c_i32, [c_vp, c_i32, c_i64]),
+    "sketch_batched_gemm": (c_i32, [c_vp, c_vp, c_i32, c_vp]),
+    "sketch_batched_qr": (c_i32, [c_vp, c_vp, c_i32, c_vp]),
+    "sketch_batched_id": (c_i32, [c_vp, c_vp, c_i32, c_vp]),
+    "sketch_batched_norm": (c_i32, [c_vp, c_vp, c_i32, c_vp]),
+    "sketch_batched_gather": (c_i32, [c_vp, c_vp, c_i32, c_vp]),
+    "sketch_get_rows_device": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp]),
     "sketch_test_poison_lds": (c_i32, [c_vp, ctypes.c_uint32, c_vp]),
     "sketch_profile_enable": (c_i32, [c_vp, c_i32]),
     "sketch_profile_read": (c_i32, [c_vp, ctypes.c_char_p, P(ctypes.c_double), P(c_i64), c_i32]),
