@@ -122,6 +122,7 @@ static int dispatch(Ctx* c, const GatherCfg& cfg, const T* A, int64_t lda, int64
     SK_TRY_NW(32, 1, 256)
     SK_TRY_NW(64, 1, 256)
     SK_TRY(16, 16, 1, 64) SK_TRY(16, 16, 1, 128) SK_TRY(16, 16, 1, 256)
+    SK_TRY(16, 16, 4, 64) SK_TRY(16, 16, 2, 128)
   } else {
     SK_TRY_NW(16, 2, 64)
     SK_TRY_NW(16, 1, 64)
@@ -131,6 +132,7 @@ static int dispatch(Ctx* c, const GatherCfg& cfg, const T* A, int64_t lda, int64
     SK_TRY_NW(16, 1, 256)
     SK_TRY_NW(32, 1, 256)
     SK_TRY(16, 16, 1, 64) SK_TRY(16, 16, 1, 128) SK_TRY(16, 16, 1, 256)
+    SK_TRY(16, 16, 2, 64)
   }
   set_error("internal: no SJLT kernel for NW=%d NJ=%d RPL=%d KC=%d", cfg.nw, cfg.nj, cfg.rpl, cfg.kc);
   return SK_EINVAL;
@@ -224,8 +226,18 @@ static GatherCfg choose_cfg(int dtype, int kc, int W, int g) {
   else c.rpl = kc == 64 ? 2 : 1;
   // accumulators per lane stay at or below 64 VGPRs
   int njmax = (dtype == SK_F32 ? 64 : 32) / c.rpl;
-  // a pass wider than 8 waves x njmax columns would re-read A: fewer rows per lane
+  // A pass wider than 8 waves x njmax columns: 16 waves of 16 columns keep the
+  // RPL rows per lane, one workgroup per 256 columns (A is staged once per 256
+  // columns).  One row per lane instead would double the LDS bytes per add
+  // (each bucket entry read then serves one element per lane, not RPL):
+  // measured on FP32, alpha = 8, w = 64, n = 65536, four blocks in one pass:
+  // 30.2 ms with one row per lane, 11.2 ms with four.
   if (W > 8 * njmax && c.rpl > 1) {
+    if (g % 16 == 0) {
+      c.nj = 16;
+      c.nw = 16;
+      return c;
+    }
     c.rpl = 1;
     njmax = dtype == SK_F32 ? 64 : 32;
   }

@@ -144,6 +144,26 @@ def test_extension_multiblock_and_determinism(ctx):
     sk2.release()
 
 
+@pytest.mark.parametrize("dtype,n,w,alpha,nb", [(np.float32, 2085, 64, 8, 3), (np.float32, 2085, 64, 8, 4),
+                                                 (np.float32, 1500, 64, 8, 7), (np.float32, 1100, 128, 4, 3),
+                                                 (np.float64, 1300, 64, 8, 3)])
+def test_wide_passes(ctx, dtype, n, w, alpha, nb):
+    """Passes wider than eight waves of columns (16 waves of 16 columns with
+    several rows per lane, one workgroup per 256 columns): S and S' of the new
+    blocks against the oracle, ragged n."""
+    api = _api()
+    A = workloads.random_dense(n, n, 12, dtype)
+    Ad = api.to_device_colmajor(A)
+    sk = api.Sketch(ctx, Ad, "sjlt", w, 31, alpha=alpha, transpose=True)
+    Sn, Stn = sk.extend(w, nblocks=nb)
+    torch.cuda.synchronize()
+    R = ops.operator("sjlt", n, [w] * (nb + 1), 31, alpha=alpha)[:, w:]
+    A64 = A.astype(np.float64)
+    assert osk.rel_fro(Sn.cpu().numpy().astype(np.float64), A64 @ R) <= TOL[dtype]
+    assert osk.rel_fro(Stn.cpu().numpy().astype(np.float64), A64.T @ R) <= TOL[dtype]
+    sk.release()
+
+
 def test_identity_gives_R_and_linearity(ctx):
     api = _api()
     n, w = 512, 64
