@@ -60,7 +60,8 @@ def parse():
     p.add_argument("--workload", default="cauchy16k", choices=["cauchy16k"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--leg", default="all",
-                   choices=["all", "main", "srht", "gaussian", "fp32", "mf", "batch", "precision", "hss"],
+                   choices=["all", "main", "srht", "gaussian", "fp32", "mf", "batch", "precision", "hss",
+                            "hss_device"],
                    help="run one leg only and print its figures (for profiling); 'main' = the SJLT step with "
                         "the copy and read references")
     p.add_argument("--only-main", action="store_true", help="same as --leg main")
@@ -309,6 +310,59 @@ def matrix_free_leg(api, ctx, steps, warmup):
     return out
 
 
+def hss_device_leg(api, ctx, A16=None, reps=3):
+    """Adaptive HSS compression on the GPU end to end (Algorithm 1: sketch,
+    extensions and the per-node work of every tree level in the library's
+    batched kernels; the tree walk and the decisions on the host): the n = 1024
+    Gaussian-kernel matrix (leaf 64, d0 = dd = 64, eps_r 1e-6) for each kind,
+    and the n = 16384 nonsymmetric Cauchy matrix (leaf 256, d0 = dd = 64,
+    eps_r = eps_a = 1e-8) with SJLT.  Wall time per compression (mean of
+    ``reps`` after one warm-up) and the device time of each kernel family."""
+    import torch
+
+    import workloads
+    from paper_2302_01977_amd import hss as dhss
+
+    def run(A, kind, seed, leaf, d0, dd, eps_r, eps_a, sym, alpha=4):
+        res = dhss.compress(ctx, A, kind, seed, leaf, d0, dd, eps_r, eps_a, symmetric=sym, alpha=alpha)
+        res.sketch.release()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read("", reset=True)
+        times = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            res = dhss.compress(ctx, A, kind, seed, leaf, d0, dd, eps_r, eps_a, symmetric=sym, alpha=alpha)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+            res.sketch.release()
+        kern = {}
+        for name in ("sjlt_gather", "sjlt_gather_t", "sjlt_meta", "sjlt_reduce", "srht", "srht_t", "srht_reduce",
+                     "srht_reduce_t", "gauss_f64", "gauss_f64_t", "gauss_reduce", "hss_gemm", "hss_qr", "hss_id",
+                     "hss_norm", "hss_gather", "hss_rrows"):
+            ms, cnt = ctx.profile_read(name)
+            if cnt:
+                kern[name] = {"ms_per_compression": round(ms / reps, 4), "launches_per_compression": cnt // reps}
+        ctx.profile(False)
+        sk_ms = sum(v["ms_per_compression"] for k, v in kern.items() if not k.startswith("hss_"))
+        node_ms = sum(v["ms_per_compression"] for k, v in kern.items() if k.startswith("hss_"))
+        return {"ms": round(1e3 * sum(times) / len(times), 3), "final_d": int(res.final_d),
+                "extensions": int(res.extensions), "max_rank": int(res.max_rank()), "converged": bool(res.converged),
+                "sketch_kernels_ms": round(sk_ms, 4), "per_node_kernels_ms": round(node_ms, 4), "kernels": kern}
+
+    c = workloads.cfg1()
+    A1 = api.to_device_colmajor(c["A"])
+    out = {"workload": "adaptive HSS on the GPU: n=1024 FP64 Gaussian kernel (leaf 64, d0=dd=64, eps 1e-6) per "
+                       "kind; n=16384 FP64 Cauchy (leaf 256, d0=dd=64, eps 1e-8) with SJLT alpha=4"}
+    for kind in ("sjlt", "gaussian", "srht"):
+        out["kernel1024_" + kind] = run(A1, kind, c["seed"], c["leaf"], c["d0"], c["dd"], c["eps_r"], c["eps_a"],
+                                        True, c["alpha"])
+    if A16 is None:
+        A16 = api.to_device_colmajor(workloads.cfg2()["A"])
+    out["cauchy16k_sjlt"] = run(A16, "sjlt", workloads.OP_SEED[2], 256, 64, 64, 1e-8, 1e-8, False)
+    return out
+
+
 def hss_leg(api, ctx, reps=50):
     """The n = 1024 FP64 Gaussian-kernel matrix of the adaptive HSS workload
     (points in [0,1]^2 in bisection order, h = 0.5, shift 1e-2): the sketch of
@@ -515,7 +569,8 @@ def main():
     single = {"mf": ("matrix_free", lambda ctx: matrix_free_leg(api, ctx, args.steps, args.warmup)),
               "batch": ("batched", lambda ctx: batch_leg(api, ctx, max(3, args.steps // 2), 2)),
               "precision": ("precision_65536", lambda ctx: precision_leg(api, ctx, 2)),
-              "hss": ("hss_1024", lambda ctx: hss_leg(api, ctx))}
+              "hss": ("hss_1024", lambda ctx: hss_leg(api, ctx)),
+              "hss_device": ("hss_device", lambda ctx: hss_device_leg(api, ctx))}
     if args.leg in single:
         key, fn = single[args.leg]
         ctx = api.Context(0)
@@ -624,6 +679,7 @@ def main():
         results["batched"] = batch_leg(api, ctx, max(3, args.steps // 2), 2)
         results["precision_65536"] = precision_leg(api, ctx, 2)
         results["hss_1024"] = hss_leg(api, ctx)
+        results["hss_device"] = hss_device_leg(api, ctx, A16=A)
 
     # the timed step: SJLT, S and S' of the FP64 matrix
     r = results["sjlt"]
