@@ -157,10 +157,14 @@ def test_wide_passes(ctx, dtype, n, w, alpha, nb):
     sk = api.Sketch(ctx, Ad, "sjlt", w, 31, alpha=alpha, transpose=True)
     Sn, Stn = sk.extend(w, nblocks=nb)
     torch.cuda.synchronize()
-    R = ops.operator("sjlt", n, [w] * (nb + 1), 31, alpha=alpha)[:, w:]
+    Rall = ops.operator("sjlt", n, [w] * (nb + 1), 31, alpha=alpha)
+    R = Rall[:, w:]
     A64 = A.astype(np.float64)
     assert osk.rel_fro(Sn.cpu().numpy().astype(np.float64), A64 @ R) <= TOL[dtype]
     assert osk.rel_fro(Stn.cpu().numpy().astype(np.float64), A64.T @ R) <= TOL[dtype]
+    # the apply (one block of w columns: a narrow pass)
+    assert osk.rel_fro(sk.S[:, :w].cpu().numpy().astype(np.float64), A64 @ Rall[:, :w]) <= TOL[dtype]
+    assert osk.rel_fro(sk.St[:, :w].cpu().numpy().astype(np.float64), A64.T @ Rall[:, :w]) <= TOL[dtype]
     sk.release()
 
 
