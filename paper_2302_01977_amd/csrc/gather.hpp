@@ -73,16 +73,30 @@ namespace sk {
 // four independent reads at a time; the rest of a longer bucket follows in
 // pairs (and a last single entry).
 // With PACK, E holds one word per entry instead: the address with the sign in
-// bit 31.
-template <typename T, int NJ, int RPL, typename VT, bool PACK = false>
+// bit 31.  With NEG the tile holds a negated copy of every staged source and
+// an entry is one word, the address of the source row or of its negated copy:
+// the gather adds without a sign.
+template <typename T, int NJ, int RPL, typename VT, bool PACK = false, bool NEG = false>
 __device__ __forceinline__ void gather_chunk_lds(const uint32_t* E, int ebase, uint32_t bnd, uint32_t bndN,
                                                  uint32_t lane_part, uint32_t zaddr, int ms,
                                                  T (&acc)[NJ][RPL]) {
   typedef uint32_t u4 __attribute__((ext_vector_type(4)));
   typedef __attribute__((address_space(3))) const VT* lds_vt;
   constexpr int EW = sizeof(T) == 8 ? 4 : 2;
+  // a + s x: an add when the sign is in the staged value
+  auto madd = [](T x, T s, T a) -> T {
+    if constexpr (NEG) {
+      (void)s;
+      return a + x;
+    } else {
+      return fma(x, s, a);
+    }
+  };
   auto entry = [&](int e, uint32_t& addr, T& sgn) {
-    if constexpr (PACK) {
+    if constexpr (NEG) {
+      addr = E[e] ^ lane_part;
+      sgn = T(1);
+    } else if constexpr (PACK) {
       const uint32_t w = E[e];
       addr = (w & 0x7fffffffu) ^ lane_part;
       if constexpr (sizeof(T) == 8)
@@ -120,7 +134,7 @@ __device__ __forceinline__ void gather_chunk_lds(const uint32_t* E, int ebase, u
       for (int r = 0; r < RPL; ++r) {
         T a = acc[jj][r];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a = fma(((const T*)&x[q])[r], sg[q], a);
+        for (int q = 0; q < 4; ++q) a = madd(((const T*)&x[q])[r], sg[q], a);
         acc[jj][r] = a;
       }
     };
@@ -134,7 +148,8 @@ __device__ __forceinline__ void gather_chunk_lds(const uint32_t* E, int ebase, u
       entry(e + 1, a1, s1);
       const VT x0 = *(lds_vt)(uintptr_t)a0, x1 = *(lds_vt)(uintptr_t)a1;
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) acc[jj][r] = fma(((const T*)&x1)[r], s1, fma(((const T*)&x0)[r], s0, acc[jj][r]));
+      for (int r = 0; r < RPL; ++r)
+        acc[jj][r] = madd(((const T*)&x1)[r], s1, madd(((const T*)&x0)[r], s0, acc[jj][r]));
     }
     if (e < e1) {  // odd bucket length
       uint32_t a0;
@@ -142,7 +157,7 @@ __device__ __forceinline__ void gather_chunk_lds(const uint32_t* E, int ebase, u
       entry(e, a0, s0);
       const VT x0 = *(lds_vt)(uintptr_t)a0;
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) acc[jj][r] = fma(((const T*)&x0)[r], s0, acc[jj][r]);
+      for (int r = 0; r < RPL; ++r) acc[jj][r] = madd(((const T*)&x0)[r], s0, acc[jj][r]);
     }
   }
 }

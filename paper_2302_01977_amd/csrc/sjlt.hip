@@ -5,7 +5,7 @@
 
 namespace sk {
 
-template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK, bool LDSE>
+template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK, bool LDSE, bool NEG>
 __global__ void __launch_bounds__(NW * 64)
     sjlt_gather_kernel(const T* __restrict__ A, int64_t lda, int64_t L, int64_t K, SjltPass pass,
                        T* __restrict__ out, int64_t ldo, T scale, int split, T* __restrict__ part) {
@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(NW * 64)
   }
   const int64_t jc = (int64_t)g * NJ;
   T* dst = split > 1 ? part + (int64_t)s * L * ((int64_t)pass.ngroups * NJ) + jc * L : out + jc * ldo;
-  sjlt_tile<T, TRANS, NW, NJ, RPL, KCK, LDSE>(A, lda, L, K, l0, t0, t1, active, pass.ptr[blk] + jb,
+  sjlt_tile<T, TRANS, NW, NJ, RPL, KCK, LDSE, NEG>(A, lda, L, K, l0, t0, t1, active, pass.ptr[blk] + jb,
                                               (int64_t)pass.wtot[blk] + 1, pass.ent[blk], blk, eptr[0], eptr[1],
                                               pass.kcap, pass.nblk * pass.kcap, pass.ms, dst, split > 1 ? L : ldo,
                                               split > 1 ? T(1) : scale);
@@ -66,12 +66,12 @@ void split_reduce_any(int dtype, const void* part, int split, int64_t L, int64_t
 }
 
 // ------------------------------------------------------------------ dispatch
-template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK, bool LDSE>
+template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK, bool LDSE, bool NEG = false>
 static int run_gather(Ctx* c, const T* A, int64_t lda, int64_t L, int64_t K, const SjltPass& pass, T* out,
                       int64_t ldo, T scale, int split, T* part, int gz, hipStream_t st) {
   dim3 grid((unsigned)((L + 64 * RPL - 1) / (64 * RPL)), (unsigned)split, (unsigned)gz);
-  const size_t shmem = gather_lds_bytes((int)sizeof(T), KCK, 64 * RPL, LDSE, pass.nblk, pass.kcap);
-  auto kern = sjlt_gather_kernel<T, TRANS, NW, NJ, RPL, KCK, LDSE>;
+  const size_t shmem = gather_lds_bytes((int)sizeof(T), KCK, 64 * RPL, LDSE, pass.nblk, pass.kcap, NEG);
+  auto kern = sjlt_gather_kernel<T, TRANS, NW, NJ, RPL, KCK, LDSE, NEG>;
   static bool attr_set = false;  // once per instantiation (the limit is the same on every device)
   if (!attr_set) {
     SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
@@ -89,6 +89,11 @@ static int try_cfg(const GatherCfg& cfg, Ctx* c, const T* A, int64_t lda, int64_
                    T* out, int64_t ldo, T scale, int split, T* part, int gz, hipStream_t st) {
   if (cfg.nw != NW || cfg.nj != NJ || cfg.rpl != RPL || cfg.kc != KCK) return 1;
   if constexpr (GatherValid<T, TRANS, NW, NJ, RPL, KCK>::value) {
+    if constexpr (sizeof(T) == 4 && NW == 16 && RPL > 1) {  // the wide FP32 passes
+      if (cfg.ldse && cfg.neg)
+        return run_gather<T, TRANS, NW, NJ, RPL, KCK, true, true>(c, A, lda, L, K, pass, out, ldo, scale, split,
+                                                                  part, gz, st);
+    }
     if (cfg.ldse)
       return run_gather<T, TRANS, NW, NJ, RPL, KCK, true>(c, A, lda, L, K, pass, out, ldo, scale, split, part, gz, st);
     return run_gather<T, TRANS, NW, NJ, RPL, KCK, false>(c, A, lda, L, K, pass, out, ldo, scale, split, part, gz, st);
@@ -220,7 +225,7 @@ int sjlt_chunk_for(int w, int alpha, int lam) {
 // rows per lane, columns per wave and waves per workgroup for a pass of width W
 // whose block widths share the divisor g
 static GatherCfg choose_cfg(int dtype, int kc, int W, int g) {
-  GatherCfg c;
+  GatherCfg c = {};
   c.kc = kc;
   if (dtype == SK_F32) c.rpl = kc == 64 ? 4 : kc == 128 ? 2 : 1;
   else c.rpl = kc == 64 ? 2 : 1;
@@ -331,11 +336,15 @@ int launch_sjlt_pass(Handle* h, const sk_input* in, int b0, int b1, bool trans, 
   const int TL = 64 * cfg.rpl;
   cfg.ldse = same && (int64_t)nblk * pass.kcap <= (int64_t)cfg.nw * 64 * 8 &&
              gather_lds_bytes((int)esz, cfg.kc, TL, true, nblk, pass.kcap) <= 160 * 1024;
+  // wide FP32 passes (16 waves, several rows per lane) are bound by LDS bytes:
+  // negated tile rows halve the bytes of every staged entry read
+  cfg.neg = cfg.ldse && h->dtype == SK_F32 && cfg.nw == 16 && cfg.rpl > 1 &&
+            gather_lds_bytes((int)esz, cfg.kc, TL, true, nblk, pass.kcap, true) <= 160 * 1024;
 
   const int64_t L = trans ? in->n : in->m;  // lanes
   const int64_t K = trans ? in->m : in->n;  // sources (= rows of R)
   const int64_t tiles = ((L + TL - 1) / TL) * gz;
-  const size_t tile_bytes = gather_lds_bytes((int)esz, cfg.kc, TL, cfg.ldse, nblk, pass.kcap);
+  const size_t tile_bytes = gather_lds_bytes((int)esz, cfg.kc, TL, cfg.ldse, nblk, pass.kcap, cfg.neg);
   const int64_t per_cu = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)tile_bytes);
   const int64_t target = per_cu * (int64_t)h->ctx->num_cu;
   const int ms_raw = pass.ms;

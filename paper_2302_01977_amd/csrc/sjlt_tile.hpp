@@ -73,7 +73,11 @@ struct VecT<double, 2> {
 // `blk` among the staged entry regions and this thread's staging pointers
 // eptr[2] (null when the thread stages nothing); dst points at the group's
 // first output column (leading dimension ldd), scaled by sc.
-template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK, bool LDSE>
+// NEG (FP32 with staged entries): the tile also holds the negated sources in
+// rows KCK + 1 .. 2 KCK, and an entry is one word, the address of the source
+// row or of its negated copy, so the gather adds without a sign and reads one
+// word per entry instead of two (the wide passes are bound by LDS bytes).
+template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK, bool LDSE, bool NEG = false>
 __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, int64_t L, int64_t K, int64_t l0,
                                           int t0, int t1, bool active, const int32_t* __restrict__ ptr,
                                           int64_t prow, const int32_t* __restrict__ ent, int blk,
@@ -94,8 +98,10 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
   // source of null entries), then (LDSE) the chunk's bucket entries: FP64 one
   // word (the entry's LDS address in the tile, its sign in bit 31), FP32 two
   // words (address, sign as +-1.0f).
-  constexpr int NSLOT = KCK + 1;
+  constexpr int NSLOT = NEG ? 2 * KCK + 1 : KCK + 1;
   constexpr bool PACK = SZ == 8;
+  constexpr bool ONEW = PACK || NEG;  // one word per staged entry
+  static_assert(!NEG || (LDSE && SZ == 4), "negated rows: FP32 with staged entries");
   extern __shared__ __attribute__((aligned(16))) char smem[];
   T* tile = (T*)smem;
   uint32_t* ents = (uint32_t*)(smem + NSLOT * TL * SZ);
@@ -120,7 +126,7 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
   if constexpr (LDSE) {
     if (tid < 8) {
       const uint32_t zrow = tile_lds + (uint32_t)(KCK * TL * SZ);
-      if constexpr (PACK) {
+      if constexpr (ONEW) {
         ents[epad + tid] = zrow;
       } else {
         ents[(epad + tid) * 2] = zrow;
@@ -199,11 +205,16 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const uint32_t src = ebuf[h][q] >> 1;
-          ad[q] = (tile_lds + src * (uint32_t)(TL * SZ)) | (TRANS ? ((src / VECN) & 15u) * 16u : 0u);
+          // NEG: negative entries address the negated copy (null entries, source
+          // KCK, always the zero row)
+          const uint32_t row = NEG && (ebuf[h][q] & 1u) && src < (uint32_t)KCK ? src + KCK + 1 : src;
+          ad[q] = (tile_lds + row * (uint32_t)(TL * SZ)) | (TRANS ? ((src / VECN) & 15u) * 16u : 0u);
           sg[q] = ((ebuf[h][q] & 1u) << 31) | 0x3f800000u;
         }
         const int qb = q0[h];
-        if constexpr (PACK) {
+        if constexpr (NEG) {
+          *(u32x4*)&ents[qb] = u32x4{ad[0], ad[1], ad[2], ad[3]};
+        } else if constexpr (PACK) {
           *(u32x4*)&ents[qb] = u32x4{ad[0] | (ebuf[h][0] << 31), ad[1] | (ebuf[h][1] << 31),
                                      ad[2] | (ebuf[h][2] << 31), ad[3] | (ebuf[h][3] << 31)};
         } else {
@@ -216,7 +227,12 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
     }
     if (!TRANS) {
 #pragma unroll
-      for (int it = 0; it < NV; ++it) *(u32x4*)(&tile[(my_col + it * CSTEP) * TL + my_row]) = buf[it];
+      for (int it = 0; it < NV; ++it) {
+        *(u32x4*)(&tile[(my_col + it * CSTEP) * TL + my_row]) = buf[it];
+        if constexpr (NEG)
+          *(u32x4*)(&tile[(KCK + 1 + my_col + it * CSTEP) * TL + my_row]) =
+              buf[it] ^ u32x4{0x80000000u, 0x80000000u, 0x80000000u, 0x80000000u};
+      }
     } else {
 #pragma unroll
       for (int ib = 0; ib < NV / VECN; ++ib) {
@@ -231,6 +247,11 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
 #pragma unroll
           for (int j = 0; j < VECN; ++j) rowv[j] = blkv[j][i];
           __builtin_memcpy(&tile[(my_rb * VECN + i) * TL + pos], rowv, 16);
+          if constexpr (NEG) {
+#pragma unroll
+            for (int j = 0; j < VECN; ++j) rowv[j] = -rowv[j];
+            __builtin_memcpy(&tile[(KCK + 1 + my_rb * VECN + i) * TL + pos], rowv, 16);
+          }
         }
       }
     }
@@ -273,7 +294,7 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
     if (t + 1 < t1) load_chunk(t + 1);  // in flight during the gather below
     if (active) {
       if constexpr (LDSE)
-        gather_chunk_lds<T, NJ, RPL, VT, PACK>(ents, (t - blk) * kcap, bnd, bndN, lane_part, zaddr, ms, acc);
+        gather_chunk_lds<T, NJ, RPL, VT, PACK, NEG>(ents, (t - blk) * kcap, bnd, bndN, lane_part, zaddr, ms, acc);
       else
         gather_chunk<T, NJ, RPL, VT>(ptr + (int64_t)t * prow, ent, LD, acc);
     }
@@ -289,16 +310,19 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
   }
 }
 
-// dynamic LDS of one workgroup: the tile with its zero slot, then the entries
-inline size_t gather_lds_bytes(int esz, int kc, int tl, bool ldse, int nblk, int kcap) {
-  const size_t ew = esz == 8 ? 4 : 8;
+// dynamic LDS of one workgroup: the tile with its zero slot (and with neg the
+// negated rows), then the entries
+inline size_t gather_lds_bytes(int esz, int kc, int tl, bool ldse, int nblk, int kcap, bool neg = false) {
+  const size_t ew = esz == 8 || neg ? 4 : 8;
+  const size_t rows = neg ? 2 * (size_t)kc + 1 : (size_t)kc + 1;
   // (+8 entries: the straight-line slots of the last bucket may read up to 7 past it)
-  return (size_t)(kc + 1) * tl * esz + (ldse ? ((size_t)nblk * kcap + 8) * ew : 0);
+  return rows * tl * esz + (ldse ? ((size_t)nblk * kcap + 8) * ew : 0);
 }
 
 struct GatherCfg {
   int nw, nj, rpl, kc;
   bool ldse;  // bucket entries staged in LDS (else read through the scalar cache)
+  bool neg;   // FP32 staged entries of one word with negated tile rows
 };
 
 template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK>
