@@ -168,7 +168,9 @@ int sketch_rerun_static(sk_handle *h, const sk_input *in, uint64_t seed, const s
  *                 *dh = dL/dh (one FP64 value, device), K recomputed tile by tile:
  *                 dL/dx_i = -(1/h^2) sum_j (G_ij + G_ji) K_ij (x_i - x_j),
  *                 dL/dh = sum_ij G_ij K_ij |x_i - x_j|^2 / h^3, G = W R^T.
- *                 Requires nblocks * alpha <= 16 and at most 256 columns.
+ *                 Requires alpha <= 16 and blocks of at most 256 columns;
+ *                 more blocks (over 16 hash codes per point or 256 columns in
+ *                 all) are processed in groups, the gradient summed in FP64.
  * The input must be the one the handle was applied to.  Asynchronous; uses the
  * context workspace (calls sharing a context must be ordered on one stream).
  * Errors: SK_EINVAL, SK_EUNSUPPORTED (other operator kinds), SK_ENOMEM, SK_EHIP. */

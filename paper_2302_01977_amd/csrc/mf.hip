@@ -21,6 +21,8 @@
 // combined in a fixed order, so the result is deterministic.
 #include <algorithm>
 #include <type_traits>
+#include <utility>
+#include <vector>
 
 #include "gather.hpp"
 #include "internal.hpp"
@@ -145,12 +147,16 @@ __global__ void __launch_bounds__(NW * 64)
   // kernel entries of the chunk into the tile; only the chunk that holds the
   // rows' own indices adds the diagonal shift
   auto eval = [&](int64_t k0, auto diag) {
+    // sources of this chunk that exist (a uniform 32-bit bound: scalar compares)
+    const int kn = (int)std::min<int64_t>(N - k0, (int64_t)KCK);
+    // (unrolled by 4 only: a full unroll takes the kernel past 64 VGPRs, which
+    // halves the workgroups per CU)
 #pragma unroll 4
     for (int r = 0; r < SPW; ++r) {
       const int src = wave + NW * r;
       const int64_t k = k0 + src;
       float v = 0.f;
-      if (k < N) {
+      if (src < kn) {
         const f4 q = xsl[r];
         float d2 = 0.f;
 #pragma unroll
@@ -234,16 +240,25 @@ __global__ void __launch_bounds__(256) transpose_kernel(const float* __restrict_
 // by the uniform hash of j: conflict-free); G_ji reads row j of W, which each
 // wave stages in its own LDS slot (two rows at a time, the next two already in
 // flight in registers), at the columns named by the hash of lane i.
-template <int DIM, int NWB, int MAXA>
+//
+// NA is the number of hash codes per source (blocks x alpha) rounded up to a
+// multiple of 4; the codes past the true count na carry weight 0 (scalar
+// selects, no branches), so the loop over codes is straight-line code with
+// every per-code constant hoisted: per code and pair one readlane of the
+// source's code, one address add, two FMAs.  Calls with more codes or columns
+// run in groups of blocks; `mode` tells a group whether it writes dX (0: the
+// only group), starts (1), adds to (2) or finishes (3) the FP64 sum in dXacc.
+template <int DIM, int NWB, int NA>
 __global__ void __launch_bounds__(NWB * 64)
     mf_bwd_kernel(const float* __restrict__ X, int64_t N, float c2, const float* __restrict__ W, int64_t ldw,
                   const float* __restrict__ Wrm, int Wt, MfBlocks mb, int alpha, float* __restrict__ dX,
-                  float xscale, double* __restrict__ dh_part) {
+                  float xscale, double* __restrict__ dh_part, double* __restrict__ dXacc, int mode) {
   constexpr int SRC = 2;    // sources staged per step and wave
   constexpr int GRP = 32;   // sources summed in FP32 before the FP64 accumulators
   extern __shared__ __attribute__((aligned(16))) float smem_f[];
   float* const Wr = smem_f;                   // Wr[col * 64 + lane] = W(l0 + lane, col), col < Wt
   float* const Wj = smem_f + (size_t)Wt * 64;  // per wave: SRC staged rows of Wt floats
+  typedef __attribute__((address_space(3))) const float* lds_f;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -259,33 +274,42 @@ __global__ void __launch_bounds__(NWB * 64)
   float xi[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) xi[d] = lane_ok ? X[i * DIM + d] : 0.f;
-  // this lane's own hash columns and signs (for G_ji)
-  int colL[MAXA];
-  float sgL[MAXA];
   const int na = mb.nb * alpha;
+  // per code q: the block's first column (uniform), this lane's own hash
+  // column and sign (G_ji) and the LDS addresses of that column in the wave's
+  // staged rows
+  int cof[NA];
+  float sgL[NA];
+  uint32_t gja[SRC][NA];
+  const uint32_t rows_lds = (uint32_t)(uintptr_t)(lds_f)myrows;
 #pragma unroll
-  for (int q = 0; q < MAXA; ++q) {
-    colL[q] = 0;
+  for (int q = 0; q < NA; ++q) {
+    const int b = q < na ? q / alpha : 0, c = q % alpha;
+    cof[q] = q < na ? mb.coloff[b] : 0;
+    int colL = 0;
     sgL[q] = 0.f;
     if (q < na && lane_ok) {
-      const int b = q / alpha, c = q % alpha;
       const uint32_t code = mb.codes[b][i * alpha + c];
-      colL[q] = (int)(code >> 1) + mb.coloff[b];
+      colL = (int)(code >> 1) + mb.coloff[b];
       sgL[q] = (code & 1u) ? -1.f : 1.f;
     }
+#pragma unroll
+    for (int u = 0; u < SRC; ++u) gja[u][q] = rows_lds + (uint32_t)(u * Wt + colL) * 4u;
   }
+  const uint32_t wr_lane = (uint32_t)(uintptr_t)(lds_f)Wr + (uint32_t)lane * 4u;
   __syncthreads();
 
-  // this wave's sources [js, je); rows are Wt / 4 pieces of 16 bytes
-  const int64_t js = N * wave / NWB, je = N * (wave + 1) / NWB;
+  // this wave's sources [js, js + len); rows are Wt / 4 pieces of 16 bytes
+  const int64_t js = N * wave / NWB;
+  const int len = (int)(N * (wave + 1) / NWB - js);
   const int npc = Wt / 4;
   typedef float f4v __attribute__((ext_vector_type(4)));
   f4v pf[SRC];
-  auto fetch = [&](int64_t j0) {
+  auto fetch = [&](int r0) {
 #pragma unroll
     for (int u = 0; u < SRC; ++u) {
-      const int64_t j = j0 + u;
-      pf[u] = (lane < npc && j < je) ? *(const f4v*)(Wrm + j * Wt + 4 * lane) : f4v{0.f, 0.f, 0.f, 0.f};
+      const int r = r0 + u;
+      pf[u] = (lane < npc && r < len) ? *(const f4v*)(Wrm + (js + r) * Wt + 4 * lane) : f4v{0.f, 0.f, 0.f, 0.f};
     }
   };
 
@@ -299,32 +323,32 @@ __global__ void __launch_bounds__(NWB * 64)
   // coordinates and hash codes of the sources, 64 at a time: lane r holds those
   // of source jg + r, broadcast with readlane (no scalar-memory round trip per source)
   float xg[DIM];
-  uint32_t cg[MAXA];
-  auto load_group = [&](int64_t jg) {
-    const int64_t j = jg + lane;
-    const bool ok = j < je;
+  uint32_t cg[NA];
+  auto load_group = [&](int r0) {
+    const int r = r0 + lane;
+    const bool ok = r < len;
+    const int64_t j = js + r;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) xg[d] = ok ? X[j * DIM + d] : 0.f;
 #pragma unroll
-    for (int q = 0; q < MAXA; ++q) {
+    for (int q = 0; q < NA; ++q) {
       cg[q] = 0u;
       if (q < na && ok) cg[q] = mb.codes[q / alpha][j * alpha + q % alpha];
     }
   };
-  if (js < je) fetch(js);
-  for (int64_t j0 = js; j0 < je; j0 += SRC) {
-    const int rl = (int)((j0 - js) & 63);  // lane of source j0 in the group registers
-    if (rl == 0) load_group(j0);
+  if (len > 0) fetch(0);
+  for (int r0 = 0; r0 < len; r0 += SRC) {
+    const int rl = r0 & 63;  // lane of source r0 in the group registers
+    if (rl == 0) load_group(r0);
     // stage this step's rows (the wave's earlier reads of its slot are done:
     // LDS operations of one wave complete in order), then fetch the next step
 #pragma unroll
     for (int u = 0; u < SRC; ++u)
       if (lane < npc) *(f4v*)(myrows + u * Wt + 4 * lane) = pf[u];
-    if (j0 + SRC < je) fetch(j0 + SRC);
+    if (r0 + SRC < len) fetch(r0 + SRC);
 #pragma unroll
     for (int u = 0; u < SRC; ++u) {
-      const int64_t j = j0 + u;
-      if (j >= je) break;
+      if (r0 + u >= len) break;
       float df[DIM], r2 = 0.f;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
@@ -333,16 +357,15 @@ __global__ void __launch_bounds__(NWB * 64)
       }
       const float K = __builtin_amdgcn_exp2f(-r2 * c2);
       float gij = 0.f, gji = 0.f;
-      const float* __restrict__ wrow = myrows + u * Wt;
 #pragma unroll
-      for (int q = 0; q < MAXA; ++q) {
-        if (q < na) {
-          const int b = q / alpha;
-          const uint32_t code = (uint32_t)__builtin_amdgcn_readlane((int)cg[q], rl + u);
-          const float sg = __builtin_bit_cast(float, (code << 31) | 0x3f800000u);
-          gij = fmaf(Wr[((int)(code >> 1) + mb.coloff[b]) * 64 + lane], sg, gij);
-          gji = fmaf(wrow[colL[q]], sgL[q], gji);
-        }
+      for (int q = 0; q < NA; ++q) {
+        const uint32_t code = (uint32_t)__builtin_amdgcn_readlane((int)cg[q], rl + u);
+        // +-1.0f, or +0.0f past the true code count (integer select: stays scalar)
+        const uint32_t keep = q < na ? 0xffffffffu : 0u;
+        const float sg = __builtin_bit_cast(float, ((code << 31) | 0x3f800000u) & keep);
+        const uint32_t wa = (((code >> 1) + (uint32_t)cof[q]) << 8) + wr_lane;
+        gij = fmaf(*(lds_f)(uintptr_t)wa, sg, gij);
+        gji = fmaf(*(lds_f)(uintptr_t)gja[u][q], sgL[q], gji);
       }
       const float M = (gij + gji) * K;
 #pragma unroll
@@ -379,7 +402,13 @@ __global__ void __launch_bounds__(NWB * 64)
     }
     if (lane_ok) {
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) dX[i * DIM + d] = (float)(sx[d] * (double)xscale);
+      for (int d = 0; d < DIM; ++d) {
+        const double v = sx[d] * (double)xscale;
+        if (mode == 0) dX[i * DIM + d] = (float)v;
+        else if (mode == 1) dXacc[i * DIM + d] = v;
+        else if (mode == 2) dXacc[i * DIM + d] += v;
+        else dX[i * DIM + d] = (float)(dXacc[i * DIM + d] + v);
+      }
     }
     red[DIM * 64 + lane] = sh;  // slot of wave 0, item DIM: read back below by thread 0 only
   }
@@ -518,52 +547,88 @@ int launch_mf_backward(Handle* h, const sk_input* in, int b0, int b1, const floa
                        double* dh, hipStream_t st) {
   SK_REQUIRE(h->kind == SK_SJLT, SK_EUNSUPPORTED, "the matrix-free backward uses the SJLT operator");
   const int nblk = b1 - b0;
-  SK_REQUIRE(nblk >= 1 && nblk <= MAX_PASS_BLOCKS, SK_EINVAL, "the backward covers 1..%d blocks", MAX_PASS_BLOCKS);
-  SK_REQUIRE(nblk * h->alpha <= 16, SK_EUNSUPPORTED, "the backward supports nblocks * alpha <= 16");
-  MfBlocks mb;
-  memset(&mb, 0, sizeof(mb));
-  int Wt = 0;
-  for (int b = b0; b < b1; ++b) {
-    mb.codes[b - b0] = h->blocks[b].codes;
-    mb.coloff[b - b0] = Wt;
-    Wt += h->blocks[b].w;
+  SK_REQUIRE(nblk >= 1, SK_EINVAL, "the backward covers at least one block");
+  SK_REQUIRE(h->alpha <= 16, SK_EUNSUPPORTED, "the matrix-free backward supports alpha <= 16");
+  for (int b = b0; b < b1; ++b)
+    SK_REQUIRE(h->blocks[b].w <= 256, SK_EUNSUPPORTED, "the matrix-free backward supports blocks of <= 256 columns");
+  // groups of consecutive blocks with at most 16 hash codes per source and 256
+  // columns each; every group recomputes the kernel entries and adds its part
+  // of dL/dX (FP64 across groups) and its dL/dh partials
+  std::vector<std::pair<int, int>> groups;
+  for (int p0 = b0; p0 < b1;) {
+    int p1 = p0, codes = 0, cols = 0;
+    while (p1 < b1 && p1 - p0 < MAX_PASS_BLOCKS && codes + h->alpha <= 16 && cols + h->blocks[p1].w <= 256) {
+      codes += h->alpha;
+      cols += h->blocks[p1++].w;
+    }
+    groups.emplace_back(p0, p1);
+    p0 = p1;
   }
-  mb.nb = nblk;
-  SK_REQUIRE(Wt <= 256, SK_EUNSUPPORTED, "the backward supports at most 256 sketch columns per call");
+  const int ng = (int)groups.size();
   const int64_t N = in->N;
   const int64_t nwg = (N + 63) / 64;
-  // workspace: row-major copy of W, then per-workgroup dh partials
-  const size_t wrm_bytes = ((size_t)N * Wt * 4 + 255) & ~(size_t)255;
-  if (int rc = ensure_work(h->ctx, wrm_bytes + (size_t)nwg * 8)) return rc;
+  int Wmax = 0;
+  for (auto& gp : groups) {
+    int w = 0;
+    for (int b = gp.first; b < gp.second; ++b) w += h->blocks[b].w;
+    Wmax = std::max(Wmax, w);
+  }
+  // workspace: row-major copy of the group's columns of W, the dh partials of
+  // every group, and (several groups) the FP64 sum of dL/dX
+  const size_t wrm_bytes = ((size_t)N * Wmax * 4 + 255) & ~(size_t)255;
+  const size_t dhp_bytes = ((size_t)ng * nwg * 8 + 255) & ~(size_t)255;
+  const size_t acc_bytes = ng > 1 ? (size_t)N * in->dim * 8 : 0;
+  if (int rc = ensure_work(h->ctx, wrm_bytes + dhp_bytes + acc_bytes)) return rc;
   float* Wrm = (float*)work_ptr(h->ctx);
   double* dh_part = (double*)((char*)work_ptr(h->ctx) + wrm_bytes);
-  {
-    dim3 grid((unsigned)((N + 31) / 32), (unsigned)((Wt + 31) / 32));
-    transpose_kernel<<<grid, 256, 0, st>>>(Wd, ldw, N, Wt, Wrm);
-    SK_HIP(hipGetLastError());
-  }
+  double* dXacc = ng > 1 ? (double*)((char*)work_ptr(h->ctx) + wrm_bytes + dhp_bytes) : nullptr;
   const double hh = (double)in->h;
   const float c2 = (float)(LOG2E / (2.0 * hh * hh));
   const double ga = 1.0 / sqrt((double)h->alpha);
   const float xscale = (float)(-ga / (hh * hh));
   constexpr int NWB = 8;
-  // W rows i + two staged rows j per wave; the end-of-kernel reduction reuses it
-  const size_t shmem = std::max((size_t)Wt * 64 * 4 + (size_t)NWB * 2 * Wt * 4, (size_t)NWB * 5 * 64 * 8);
-  {
+  int col0 = 0;
+  for (int gi = 0; gi < ng; ++gi) {
+    const int p0 = groups[gi].first, p1 = groups[gi].second;
+    MfBlocks mb;
+    memset(&mb, 0, sizeof(mb));
+    int Wt = 0;
+    for (int b = p0; b < p1; ++b) {
+      mb.codes[b - p0] = h->blocks[b].codes;
+      mb.coloff[b - p0] = Wt;
+      Wt += h->blocks[b].w;
+    }
+    mb.nb = p1 - p0;
+    const float* Wg = Wd + (int64_t)col0 * ldw;
+    {
+      dim3 grid((unsigned)((N + 31) / 32), (unsigned)((Wt + 31) / 32));
+      transpose_kernel<<<grid, 256, 0, st>>>(Wg, ldw, N, Wt, Wrm);
+      SK_HIP(hipGetLastError());
+    }
+    // W rows i + two staged rows j per wave; the end-of-kernel reduction reuses it
+    const size_t shmem = std::max((size_t)Wt * 64 * 4 + (size_t)NWB * 2 * Wt * 4, (size_t)NWB * 5 * 64 * 8);
+    const int na = mb.nb * h->alpha;
+    const int NAr = (na + 3) / 4 * 4;
+    const int mode = ng == 1 ? 0 : gi == 0 ? 1 : gi + 1 < ng ? 2 : 3;
     ProfScope ps(h->ctx, "mf_bwd", st);
     const dim3 grid((unsigned)nwg);
-    auto kern = in->dim == 1 ? mf_bwd_kernel<1, NWB, 16>
-                : in->dim == 2 ? mf_bwd_kernel<2, NWB, 16>
-                : in->dim == 3 ? mf_bwd_kernel<3, NWB, 16> : mf_bwd_kernel<4, NWB, 16>;
-    static bool attr_set[4] = {false, false, false, false};
-    if (!attr_set[in->dim - 1]) {
-      SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-      attr_set[in->dim - 1] = true;
-    }
-    kern<<<grid, NWB * 64, shmem, st>>>(in->X, N, c2, Wd, ldw, Wrm, Wt, mb, h->alpha, dX, xscale, dh_part);
+    typedef void (*KernT)(const float*, int64_t, float, const float*, int64_t, const float*, int, MfBlocks, int,
+                          float*, float, double*, double*, int);
+    KernT kern = nullptr;
+#define SK_MFB(D_)                                                                                               \
+  if (in->dim == D_)                                                                                             \
+    kern = NAr == 4 ? mf_bwd_kernel<D_, NWB, 4> : NAr == 8 ? mf_bwd_kernel<D_, NWB, 8>                          \
+         : NAr == 12 ? mf_bwd_kernel<D_, NWB, 12> : mf_bwd_kernel<D_, NWB, 16>;
+    SK_MFB(1) SK_MFB(2) SK_MFB(3) SK_MFB(4)
+#undef SK_MFB
+    SK_REQUIRE(kern, SK_EINVAL, "internal: no matrix-free backward for dim %d", in->dim);
+    SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    kern<<<grid, NWB * 64, shmem, st>>>(in->X, N, c2, Wg, ldw, Wrm, Wt, mb, h->alpha, dX, xscale,
+                                        dh_part + (size_t)gi * nwg, dXacc, mode);
     SK_HIP(hipGetLastError());
+    col0 += Wt;
   }
-  dh_reduce_kernel<<<1, 64, 0, st>>>(dh_part, nwg, ga / (hh * hh * hh), dh);
+  dh_reduce_kernel<<<1, 64, 0, st>>>(dh_part, (int64_t)ng * nwg, ga / (hh * hh * hh), dh);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }

@@ -76,6 +76,34 @@ def test_backward_matches_fp64_reference(ctx, N, dim, d, alpha):
     sk.release()
 
 
+@pytest.mark.parametrize("N,w,nb,alpha", [(1500, 64, 5, 4), (1100, 128, 3, 8), (900, 48, 1, 3), (700, 48, 3, 3)])
+def test_backward_block_groups(ctx, N, w, nb, alpha):
+    """Backward over several blocks: more than 16 hash codes per point or 256
+    columns run in groups of blocks (dL/dX summed in FP64 across groups); a code
+    count that is not a multiple of four pads with zero-weight codes.  W has mean
+    one: with zero-mean W the groups' dL/dh parts cancel (about +-5650 summing to
+    -11 in the first case), which makes a relative check of dL/dh at FP32 inputs
+    ill-conditioned; with mean one every group's part has the same sign, so a
+    group dropped or counted twice still fails by O(1)."""
+    api = _api()
+    X = _points(N, 3, 21)
+    h = 0.25
+    sk = api.Sketch(ctx, None, "sjlt", w, 40, alpha=alpha, points=(torch.from_numpy(X).cuda(), h, 0.0))
+    if nb > 1:
+        sk.extend(w, nblocks=nb - 1)
+    d = w * nb
+    W = (workloads.random_dense(N, d, 22, np.float32) + np.float32(1.0)).astype(np.float32)
+    dX, dh = sk.adjoint(api.to_device_colmajor(W))
+    torch.cuda.synchronize()
+    R = ops.operator("sjlt", N, [w] * nb, 40, alpha=alpha)
+    rX, rh = osk.kernel_grad(X.astype(np.float64), _f32(h), R, W.astype(np.float64))
+    ex = osk.rel_fro(dX.cpu().numpy(), rX)
+    eh = abs(float(dh.cpu()) - rh) / abs(rh)
+    print("backward groups N=%d d=%d alpha=%d rel.err dX %.2e dh %.2e" % (N, d, alpha, ex, eh))
+    assert ex <= 1e-6 and eh <= 1e-6
+    sk.release()
+
+
 def test_gradient_against_central_differences(ctx):
     """The n = 2048 subset of the N = 32768 point set at the workload's d = 256:
     GPU gradient against FP64 central differences (step 1e-4) of the FP64 loss,
