@@ -29,21 +29,28 @@
 
 namespace sk {
 
-template <int NW, int NJ, int KCK, int DIM, bool LDSE>
+// RPL consecutive points i per lane (TL = 64 RPL per workgroup): the gather's
+// per-entry work (address, mask, bounds) is shared by RPL additions.
+template <int NW, int NJ, int KCK, int DIM, bool LDSE, int RPL>
 __global__ void __launch_bounds__(NW * 64)
     mf_sjlt_kernel(const float* __restrict__ X, int64_t N, float c2, float shift, SjltPass pass,
                    float* __restrict__ out, int64_t ldo, float scale, int split, float* __restrict__ part) {
+  constexpr int TL = 64 * RPL;
+  constexpr uint32_t ROWB = TL * 4;  // bytes of one staged source row
+  static_assert(KCK % TL == 0, "a tile's own points lie in one chunk");
+  typedef typename std::conditional<RPL == 1, float, float __attribute__((ext_vector_type(2)))>::type VT;
+  static_assert(RPL == 1 || RPL == 2, "one or two points per lane");
   // dynamic LDS: the tile (slot KCK: zeros for null entries), then (LDSE) the
   // chunk's bucket entries as (LDS address of the source row, +-1.0f)
   extern __shared__ __attribute__((aligned(16))) char smem[];
   float* const tile = (float*)smem;
-  uint32_t* const ents = (uint32_t*)(smem + (KCK + 1) * 64 * 4);
+  uint32_t* const ents = (uint32_t*)(smem + (KCK + 1) * ROWB);
   // null entries (zero row, +1.0f) in the 8 slots past the staged regions,
   // which the straight-line slots of the last bucket may read
   if constexpr (LDSE) {
     if (threadIdx.x < 8) {
       const int q = pass.nblk * pass.kcap + (int)threadIdx.x;
-      ents[q * 2] = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char*)smem + (uint32_t)(KCK * 256);
+      ents[q * 2] = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char*)smem + (uint32_t)KCK * ROWB;
       ents[q * 2 + 1] = 0x3f800000u;
     }
   }
@@ -52,8 +59,8 @@ __global__ void __launch_bounds__(NW * 64)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t l0 = (int64_t)blockIdx.x * 64;
-  const int64_t i = l0 + lane;
+  const int64_t l0 = (int64_t)blockIdx.x * TL;
+  const int64_t i0 = l0 + (int64_t)lane * RPL;  // this lane's first point
   const int s = blockIdx.y;
   const int nT = pass.nT;
   const int t0 = (int)(((int64_t)nT * s) / split);
@@ -66,10 +73,12 @@ __global__ void __launch_bounds__(NW * 64)
   const int32_t* __restrict__ ptr = pass.ptr[blk] + jb;
   const int32_t* __restrict__ ent = pass.ent[blk];
 
-  float xi[DIM];
+  float xi[RPL][DIM];
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) xi[d] = i < N ? X[i * DIM + d] : 0.f;
-  if (tid < 64) tile[KCK * 64 + tid] = 0.f;
+  for (int r = 0; r < RPL; ++r)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xi[r][d] = i0 + r < N ? X[(i0 + r) * DIM + d] : 0.f;
+  for (int e = tid; e < TL; e += NTHR) tile[KCK * TL + e] = 0.f;
 
   // LDSE staging (as in the stored-A kernels): thread tid moves entries
   // [4 tid, 4 tid + 4) and [4 (tid + NTHR), ...) of the pass's chunk regions,
@@ -103,7 +112,7 @@ __global__ void __launch_bounds__(NW * 64)
       uint32_t ad[4], sg[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        ad[q] = tile_lds + (ebuf[h][q] >> 1) * 256u;
+        ad[q] = tile_lds + (ebuf[h][q] >> 1) * ROWB;
         sg[q] = ((ebuf[h][q] & 1u) << 31) | 0x3f800000u;
       }
       const int qb = (tid + h * NTHR) * 4;
@@ -114,13 +123,15 @@ __global__ void __launch_bounds__(NW * 64)
     bndN = bndN_nx;
   };
 
-  float acc[NJ][1];
+  float acc[NJ][RPL];
 #pragma unroll
-  for (int jj = 0; jj < NJ; ++jj) acc[jj][0] = 0.f;
-  const uint32_t lane_off = (uint32_t)lane * 4u;
-  const uint32_t zaddr = (tile_lds + (uint32_t)(KCK * 256)) ^ lane_off;
+  for (int jj = 0; jj < NJ; ++jj)
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) acc[jj][r] = 0.f;
+  const uint32_t lane_off = (uint32_t)lane * RPL * 4u;
+  const uint32_t zaddr = (tile_lds + (uint32_t)KCK * ROWB) ^ lane_off;
   const char* tbase = (const char*)tile;
-  auto LD = [&](int v) -> float { return *(const float*)(tbase + ((uint32_t)v >> 1) * 256u + lane_off); };
+  auto LD = [&](int v) -> VT { return *(const VT*)(tbase + ((uint32_t)v >> 1) * ROWB + lane_off); };
 
   // the wave's sources of a chunk are src = wave + NW r (r < SPW); lane r
   // loads the coordinates of source r one chunk ahead and parks them in the
@@ -130,7 +141,7 @@ __global__ void __launch_bounds__(NW * 64)
   constexpr int SPW = KCK / NW;
   static_assert(SPW <= 64 && KCK % NW == 0 && DIM <= 4, "one source per lane");
   typedef float f4 __attribute__((ext_vector_type(4)));
-  f4* const xsl = (f4*)(smem + (size_t)(KCK + 1) * 64 * 4 + (LDSE ? ((size_t)pass.nblk * pass.kcap + 8) * 8 : 0)) +
+  f4* const xsl = (f4*)(smem + (size_t)(KCK + 1) * ROWB + (LDSE ? ((size_t)pass.nblk * pass.kcap + 8) * 8 : 0)) +
                   wave * SPW;
   float xs[DIM];
   auto load_xs = [&](int t) {
@@ -155,23 +166,30 @@ __global__ void __launch_bounds__(NW * 64)
     for (int r = 0; r < SPW; ++r) {
       const int src = wave + NW * r;
       const int64_t k = k0 + src;
-      float v = 0.f;
+      float v[RPL];
+#pragma unroll
+      for (int p = 0; p < RPL; ++p) v[p] = 0.f;
       if (src < kn) {
         const f4 q = xsl[r];
-        float d2 = 0.f;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          const float df = xi[d] - q[d];
-          d2 = fmaf(df, df, d2);
+        for (int p = 0; p < RPL; ++p) {
+          float d2 = 0.f;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            const float df = xi[p][d] - q[d];
+            d2 = fmaf(df, df, d2);
+          }
+          v[p] = __builtin_amdgcn_exp2f(-d2 * c2);
+          if constexpr (decltype(diag)::value)
+            if (k == i0 + p) v[p] += shift;
         }
-        v = __builtin_amdgcn_exp2f(-d2 * c2);
-        if constexpr (decltype(diag)::value)
-          if (k == i) v += shift;
       }
-      tile[src * 64 + lane] = v;
+      VT vv;
+      __builtin_memcpy(&vv, v, sizeof(VT));
+      *(VT*)(tile + src * TL + lane * RPL) = vv;
     }
   };
-  const int tdiag = (int)(l0 / KCK);  // KCK is a multiple of 64: the tile's rows lie in one chunk
+  const int tdiag = (int)(l0 / KCK);  // KCK is a multiple of TL: the tile's rows lie in one chunk
 
   if (t0 < t1) {
     if (LDSE) load_meta(t0);
@@ -189,22 +207,27 @@ __global__ void __launch_bounds__(NW * 64)
     __syncthreads();
     if (active) {
       if constexpr (LDSE)
-        gather_chunk_lds<float, NJ, 1, float>(ents, (t - blk) * pass.kcap, bnd, bndN, lane_off, zaddr, pass.ms,
-                                              acc);
+        gather_chunk_lds<float, NJ, RPL, VT>(ents, (t - blk) * pass.kcap, bnd, bndN, lane_off, zaddr, pass.ms,
+                                             acc);
       else
-        gather_chunk<float, NJ, 1, float>(ptr + (int64_t)t * prow, ent, LD, acc);
+        gather_chunk<float, NJ, RPL, VT>(ptr + (int64_t)t * prow, ent, LD, acc);
     }
     if (t + 1 < t1) store_xs();  // this wave's evaluation of chunk t is done
   }
-  if (!active || i >= N) return;
+  if (!active) return;
   const int64_t jc = (int64_t)g * NJ;
-  if (split == 1) {
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) out[i + (jc + jj) * ldo] = acc[jj][0] * scale;
-  } else {
-    float* p = part + (int64_t)s * N * ((int64_t)pass.ngroups * NJ);
+  for (int p = 0; p < RPL; ++p) {
+    const int64_t i = i0 + p;
+    if (i >= N) continue;
+    if (split == 1) {
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) p[i + (jc + jj) * N] = acc[jj][0];
+      for (int jj = 0; jj < NJ; ++jj) out[i + (jc + jj) * ldo] = acc[jj][p] * scale;
+    } else {
+      float* q = part + (int64_t)s * N * ((int64_t)pass.ngroups * NJ);
+#pragma unroll
+      for (int jj = 0; jj < NJ; ++jj) q[i + (jc + jj) * N] = acc[jj][p];
+    }
   }
 }
 
@@ -428,16 +451,22 @@ __global__ void dh_reduce_kernel(const double* __restrict__ part, int64_t np, do
 }
 
 // ------------------------------------------------------------------ launch
-template <int NW, int NJ, int KCK, bool LDSE>
+// dynamic LDS of the forward: tile with its zero slot, (ldse) the entries, the
+// per-wave source coordinates
+static size_t mf_lds_bytes(int kc, int rpl, bool ldse, int nblk, int kcap) {
+  return (size_t)(kc + 1) * 64 * rpl * 4 + (ldse ? ((size_t)nblk * kcap + 8) * 8 : 0) + (size_t)kc * 16;
+}
+
+template <int NW, int NJ, int KCK, bool LDSE, int RPL = 1>
 static int run_mf(Ctx* c, int dim, const float* X, int64_t N, float c2, float shift, const SjltPass& pass,
                   float* out, int64_t ldo, float scale, int split, float* part, int gz, hipStream_t st) {
-  dim3 grid((unsigned)((N + 63) / 64), (unsigned)split, (unsigned)gz);
+  constexpr int TL = 64 * RPL;
+  dim3 grid((unsigned)((N + TL - 1) / TL), (unsigned)split, (unsigned)gz);
   // tile with its zero slot, (LDSE) the entries, the per-wave source coordinates
-  const size_t shmem =
-      (size_t)(KCK + 1) * 64 * 4 + (LDSE ? ((size_t)pass.nblk * pass.kcap + 8) * 8 : 0) + (size_t)KCK * 16;
-  auto kern = dim == 1 ? mf_sjlt_kernel<NW, NJ, KCK, 1, LDSE>
-              : dim == 2 ? mf_sjlt_kernel<NW, NJ, KCK, 2, LDSE>
-              : dim == 3 ? mf_sjlt_kernel<NW, NJ, KCK, 3, LDSE> : mf_sjlt_kernel<NW, NJ, KCK, 4, LDSE>;
+  const size_t shmem = mf_lds_bytes(KCK, RPL, LDSE, pass.nblk, pass.kcap);
+  auto kern = dim == 1 ? mf_sjlt_kernel<NW, NJ, KCK, 1, LDSE, RPL>
+              : dim == 2 ? mf_sjlt_kernel<NW, NJ, KCK, 2, LDSE, RPL>
+              : dim == 3 ? mf_sjlt_kernel<NW, NJ, KCK, 3, LDSE, RPL> : mf_sjlt_kernel<NW, NJ, KCK, 4, LDSE, RPL>;
   static bool attr_set[4] = {false, false, false, false};
   if (!attr_set[dim - 1]) {
     SK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
@@ -492,20 +521,6 @@ int launch_mf_pass(Handle* h, const sk_input* in, int b0, int b1, void* out, int
     }
   }
   const int64_t N = in->N;
-  const int64_t tiles = ((N + 63) / 64) * gz;
-  const size_t tile_bytes = (size_t)h->kc * 64 * 4;
-  const int64_t per_cu = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)tile_bytes);
-  const int64_t target = per_cu * (int64_t)h->ctx->num_cu;
-  int split = 1;
-  if (tiles < target) split = (int)std::min<int64_t>((target + tiles - 1) / tiles, std::max(1, pass.nT / 4));
-  float* part = nullptr;
-  if (split > 1) {
-    if (int rc = ensure_work(h->ctx, (size_t)split * (size_t)N * (size_t)W * 4)) return rc;
-    part = (float*)work_ptr(h->ctx);
-  }
-  const float c2 = (float)(LOG2E / (2.0 * (double)in->h * (double)in->h));
-  const float scale = (float)(1.0 / sqrt((double)h->alpha));
-  int rc = SK_EINVAL;
   const int kc = h->kc;
   // bucket entries staged in LDS (four per thread and staging round, one chunk
   // ahead) when every block of the pass has the same chunk region size
@@ -519,20 +534,45 @@ int launch_mf_pass(Handle* h, const sk_input* in, int b0, int b1, void* out, int
     pass.ms = lam2 >= 14 ? 8 : 4;
   }
   const bool ldse = same && (int64_t)nblk * pass.kcap <= (int64_t)nw * 64 * 8 &&
-                    (size_t)(kc + 1) * 64 * 4 + ((size_t)nblk * pass.kcap + 8) * 8 + (size_t)kc * 16 <= 160 * 1024;
+                    mf_lds_bytes(kc, 1, true, nblk, pass.kcap) <= 160 * 1024;
+  // wide passes: two points per lane when the 128-point tile fits beside the
+  // entries (one workgroup of 16 waves per CU): every staged entry then serves
+  // two additions, which halves the gather's address, mask and bound work
+  const int rpl = ldse && wide && kc >= 128 && mf_lds_bytes(kc, 2, true, nblk, pass.kcap) <= 160 * 1024 ? 2 : 1;
+  const int64_t tiles = ((N + 64 * rpl - 1) / (64 * rpl)) * gz;
+  const size_t tile_bytes = mf_lds_bytes(kc, rpl, ldse, nblk, pass.kcap);
+  const int64_t per_cu = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)tile_bytes);
+  const int64_t target = per_cu * (int64_t)h->ctx->num_cu;
+  int split = 1;
+  if (tiles < target) split = (int)std::min<int64_t>((target + tiles - 1) / tiles, std::max(1, pass.nT / 4));
+  float* part = nullptr;
+  if (split > 1) {
+    if (int rc = ensure_work(h->ctx, (size_t)split * (size_t)N * (size_t)W * 4)) return rc;
+    part = (float*)work_ptr(h->ctx);
+  }
+  const float c2 = (float)(LOG2E / (2.0 * (double)in->h * (double)in->h));
+  const float scale = (float)(1.0 / sqrt((double)h->alpha));
+  int rc = SK_EINVAL;
 #define SK_MF(NW_, NJ_, KC_)                                                                                          \
-  if (nw == NW_ && nj == NJ_ && kc == KC_)                                                                            \
+  if (nw == NW_ && nj == NJ_ && kc == KC_ && rpl == 1)                                                                \
     rc = ldse ? run_mf<NW_, NJ_, KC_, true>(h->ctx, in->dim, in->X, N, c2, in->shift, pass, (float*)out, ldo, scale, \
                                             split, part, gz, st)                                                     \
               : run_mf<NW_, NJ_, KC_, false>(h->ctx, in->dim, in->X, N, c2, in->shift, pass, (float*)out, ldo, scale, \
                                              split, part, gz, st);                                                   \
   else
+#define SK_MF2(NW_, NJ_, KC_)                                                                                        \
+  if (nw == NW_ && nj == NJ_ && kc == KC_ && rpl == 2)                                                               \
+    rc = run_mf<NW_, NJ_, KC_, true, 2>(h->ctx, in->dim, in->X, N, c2, in->shift, pass, (float*)out, ldo, scale,    \
+                                        split, part, gz, st);                                                       \
+  else
   SK_MF(4, 16, 64) SK_MF(8, 16, 64) SK_MF(4, 32, 64) SK_MF(8, 32, 64)
   SK_MF(4, 16, 128) SK_MF(8, 16, 128) SK_MF(4, 32, 128) SK_MF(8, 32, 128)
   SK_MF(4, 16, 256) SK_MF(8, 16, 256) SK_MF(4, 32, 256) SK_MF(8, 32, 256)
-  SK_MF(16, 16, 64) SK_MF(16, 16, 128) SK_MF(16, 16, 256) {
-    set_error("internal: no matrix-free kernel for NW=%d NJ=%d KC=%d", nw, nj, kc);
+  SK_MF(16, 16, 64) SK_MF(16, 16, 128) SK_MF(16, 16, 256)
+  SK_MF2(16, 16, 128) SK_MF2(16, 16, 256) {
+    set_error("internal: no matrix-free kernel for NW=%d NJ=%d KC=%d RPL=%d", nw, nj, kc, rpl);
   }
+#undef SK_MF2
 #undef SK_MF
   if (rc) return rc;
   if (split > 1) {
