@@ -31,9 +31,11 @@ namespace sk {
 
 // RPL consecutive points i per lane (TL = 64 RPL per workgroup): the gather's
 // per-entry work (address, mask, bounds) is shared by RPL additions.
+// cs = sqrt(log2(e) / (2 h^2)): coordinates are scaled by cs as they are
+// loaded, so that K = exp2(-|cs x_i - cs x_k|^2) needs no multiply per pair.
 template <int NW, int NJ, int KCK, int DIM, bool LDSE, int RPL>
 __global__ void __launch_bounds__(NW * 64)
-    mf_sjlt_kernel(const float* __restrict__ X, int64_t N, float c2, float shift, SjltPass pass,
+    mf_sjlt_kernel(const float* __restrict__ X, int64_t N, float cs, float shift, SjltPass pass,
                    float* __restrict__ out, int64_t ldo, float scale, int split, float* __restrict__ part) {
   constexpr int TL = 64 * RPL;
   constexpr uint32_t ROWB = TL * 4;  // bytes of one staged source row
@@ -77,7 +79,7 @@ __global__ void __launch_bounds__(NW * 64)
 #pragma unroll
   for (int r = 0; r < RPL; ++r)
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) xi[r][d] = i0 + r < N ? X[(i0 + r) * DIM + d] : 0.f;
+    for (int d = 0; d < DIM; ++d) xi[r][d] = i0 + r < N ? X[(i0 + r) * DIM + d] * cs : 0.f;
   for (int e = tid; e < TL; e += NTHR) tile[KCK * TL + e] = 0.f;
 
   // LDSE staging (as in the stored-A kernels): thread tid moves entries
@@ -147,7 +149,7 @@ __global__ void __launch_bounds__(NW * 64)
   auto load_xs = [&](int t) {
     const int64_t k = (int64_t)t * KCK + wave + NW * lane;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) xs[d] = (lane < SPW && k < N) ? X[k * DIM + d] : 0.f;
+    for (int d = 0; d < DIM; ++d) xs[d] = (lane < SPW && k < N) ? X[k * DIM + d] * cs : 0.f;
   };
   auto store_xs = [&]() {
     f4 q = f4{0.f, 0.f, 0.f, 0.f};
@@ -179,7 +181,7 @@ __global__ void __launch_bounds__(NW * 64)
             const float df = xi[p][d] - q[d];
             d2 = fmaf(df, df, d2);
           }
-          v[p] = __builtin_amdgcn_exp2f(-d2 * c2);
+          v[p] = __builtin_amdgcn_exp2f(-d2);
           if constexpr (decltype(diag)::value)
             if (k == i0 + p) v[p] += shift;
         }
@@ -458,7 +460,7 @@ static size_t mf_lds_bytes(int kc, int rpl, bool ldse, int nblk, int kcap) {
 }
 
 template <int NW, int NJ, int KCK, bool LDSE, int RPL = 1>
-static int run_mf(Ctx* c, int dim, const float* X, int64_t N, float c2, float shift, const SjltPass& pass,
+static int run_mf(Ctx* c, int dim, const float* X, int64_t N, float cs, float shift, const SjltPass& pass,
                   float* out, int64_t ldo, float scale, int split, float* part, int gz, hipStream_t st) {
   constexpr int TL = 64 * RPL;
   dim3 grid((unsigned)((N + TL - 1) / TL), (unsigned)split, (unsigned)gz);
@@ -473,7 +475,7 @@ static int run_mf(Ctx* c, int dim, const float* X, int64_t N, float c2, float sh
     attr_set[dim - 1] = true;
   }
   ProfScope ps(c, "mf_fwd", st);
-  kern<<<grid, NW * 64, shmem, st>>>(X, N, c2, shift, pass, out, ldo, scale, split, part);
+  kern<<<grid, NW * 64, shmem, st>>>(X, N, cs, shift, pass, out, ldo, scale, split, part);
   SK_HIP(hipGetLastError());
   return SK_OK;
 }
@@ -550,19 +552,19 @@ int launch_mf_pass(Handle* h, const sk_input* in, int b0, int b1, void* out, int
     if (int rc = ensure_work(h->ctx, (size_t)split * (size_t)N * (size_t)W * 4)) return rc;
     part = (float*)work_ptr(h->ctx);
   }
-  const float c2 = (float)(LOG2E / (2.0 * (double)in->h * (double)in->h));
+  const float cs = (float)sqrt(LOG2E / (2.0 * (double)in->h * (double)in->h));
   const float scale = (float)(1.0 / sqrt((double)h->alpha));
   int rc = SK_EINVAL;
 #define SK_MF(NW_, NJ_, KC_)                                                                                          \
   if (nw == NW_ && nj == NJ_ && kc == KC_ && rpl == 1)                                                                \
-    rc = ldse ? run_mf<NW_, NJ_, KC_, true>(h->ctx, in->dim, in->X, N, c2, in->shift, pass, (float*)out, ldo, scale, \
+    rc = ldse ? run_mf<NW_, NJ_, KC_, true>(h->ctx, in->dim, in->X, N, cs, in->shift, pass, (float*)out, ldo, scale, \
                                             split, part, gz, st)                                                     \
-              : run_mf<NW_, NJ_, KC_, false>(h->ctx, in->dim, in->X, N, c2, in->shift, pass, (float*)out, ldo, scale, \
+              : run_mf<NW_, NJ_, KC_, false>(h->ctx, in->dim, in->X, N, cs, in->shift, pass, (float*)out, ldo, scale, \
                                              split, part, gz, st);                                                   \
   else
 #define SK_MF2(NW_, NJ_, KC_)                                                                                        \
   if (nw == NW_ && nj == NJ_ && kc == KC_ && rpl == 2)                                                               \
-    rc = run_mf<NW_, NJ_, KC_, true, 2>(h->ctx, in->dim, in->X, N, c2, in->shift, pass, (float*)out, ldo, scale,    \
+    rc = run_mf<NW_, NJ_, KC_, true, 2>(h->ctx, in->dim, in->X, N, cs, in->shift, pass, (float*)out, ldo, scale,    \
                                         split, part, gz, st);                                                       \
   else
   SK_MF(4, 16, 64) SK_MF(8, 16, 64) SK_MF(4, 32, 64) SK_MF(8, 32, 64)
