@@ -300,11 +300,12 @@ int sketch_apply_batched(sk_ctx *ctx, const sk_input *ins, const sk_op_desc *op,
  * columns for the stopping test of section 3 (eq. "stopping_criteria-1"), the
  * interpolative decomposition by column-pivoted QR, and the local operators
  * R_tau = U_tau^T R(...).  Each call takes a host array of `count` descriptors,
- * one per node (sizes may differ), copies it to the device on `stream` (the
- * call waits for that copy) and enqueues one launch for the batch.  All
+ * one per node (sizes may differ), and enqueues the batch on `stream` with the
+ * descriptors in the kernel arguments (one launch per 40-96 descriptors); it
+ * does not wait for the device, and the host array may be reused on return.  All
  * matrices are FP64, column-major, in device memory owned by the caller.
  * Errors: SK_ESTATE (context), SK_EINVAL (a descriptor out of range; its index
- * is in the message), SK_ENOMEM, SK_EHIP. */
+ * is in the message), SK_EHIP. */
 typedef struct {
   int32_t m, n, k;        /* C is m x n; op(A) is m x k, op(B) k x n */
   int32_t transA, transB; /* nonzero: op(X) = X^T */

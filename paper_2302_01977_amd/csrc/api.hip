@@ -417,7 +417,6 @@ int sketch_finalize(sk_ctx* ctx) {
   SK_REQUIRE(ctx->c.live_handles == 0, SK_ESTATE, "%d handles still live", ctx->c.live_handles);
   SK_HIP(hipDeviceSynchronize());
   if (ctx->c.work) (void)hipFree(ctx->c.work);
-  if (ctx->c.desc_buf) (void)hipFree(ctx->c.desc_buf);
   for (auto& r : ctx->c.recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);

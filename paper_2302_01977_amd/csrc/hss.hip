@@ -5,9 +5,11 @@
 // the column-pivoted QR of the interpolative decomposition, Frobenius norms,
 // row / column selections, and the rows of R on the device.
 //
-// Every kernel takes an array of descriptors in device memory, one per node of
-// a tree level, and runs one workgroup (or a grid of tiles) per descriptor;
-// sizes are per descriptor, so the nodes of a level need not match.
+// Every kernel takes its descriptors by value in the kernel arguments (one per
+// node of a tree level; a call with more runs several launches), so a batched
+// call copies nothing and never waits for the device; it runs one workgroup
+// (or a grid of tiles) per descriptor, and sizes are per descriptor, so the
+// nodes of a level need not match.
 #include <string.h>
 
 #include <algorithm>
@@ -17,13 +19,27 @@
 
 namespace sk {
 
+// descriptors of one launch, passed by value (kernel arguments stay under 4 KB)
+template <typename D, int CAP>
+struct DescPack {
+  D d[CAP];
+};
+constexpr int CAP_GEMM = 40, CAP_QR = 64, CAP_ID = 48, CAP_NORM = 96, CAP_GATHER = 40;
+static_assert(sizeof(DescPack<sk_gemm_desc, CAP_GEMM>) <= 3584 && sizeof(DescPack<sk_qr_desc, CAP_QR>) <= 3584 &&
+                  sizeof(DescPack<sk_id_desc, CAP_ID>) <= 3584 && sizeof(DescPack<sk_norm_desc, CAP_NORM>) <= 3584 &&
+                  sizeof(DescPack<sk_gather_desc, CAP_GATHER>) <= 3584,
+              "descriptor packs fit the kernel arguments");
+
+// QR, ID and norms: one workgroup of NT threads (NWV waves) per node
+constexpr int NT = 1024, NWV = NT / 64;
+
 // ------------------------------------------------------------------ products
 // C = beta C + alpha op(A) op(B): 64 x 64 output tiles, 256 threads, each
 // thread 4 x 4 outputs; k in steps of 16 staged in LDS.
 constexpr int GT = 64, GK = 16;
 
-__global__ void __launch_bounds__(256) bgemm_kernel(const sk_gemm_desc* __restrict__ descs) {
-  const sk_gemm_desc g = descs[blockIdx.z];
+__global__ void __launch_bounds__(256) bgemm_kernel(const DescPack<sk_gemm_desc, CAP_GEMM> pk) {
+  const sk_gemm_desc g = pk.d[blockIdx.z];
   const int tm = (g.m + GT - 1) / GT, tn = (g.n + GT - 1) / GT;
   if ((int)blockIdx.x >= tm * tn) return;
   const int i0 = ((int)blockIdx.x % tm) * GT, j0 = ((int)blockIdx.x / tm) * GT;
@@ -78,7 +94,7 @@ __global__ void __launch_bounds__(256) bgemm_kernel(const sk_gemm_desc* __restri
 }
 
 // ------------------------------------------------------------------ helpers
-// sum over the workgroup (256 threads) in a fixed order; every thread gets it
+// sum over the workgroup (NT threads) in a fixed order; every thread gets it
 __device__ __forceinline__ double wg_sum(double v, double* red) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 #pragma unroll
@@ -86,7 +102,10 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
   __syncthreads();  // red is free
   if (lane == 0) red[w] = v;
   __syncthreads();
-  return (red[0] + red[1]) + (red[2] + red[3]);
+  double t = 0.0;
+#pragma unroll
+  for (int u = 0; u < NWV; ++u) t += red[u];
+  return t;
 }
 
 // Householder reflector of x = M(k:m, col): on exit M(k, col) holds beta
@@ -97,7 +116,7 @@ __device__ double house(double* __restrict__ M, int64_t ld, int m, int k, int co
   const int tid = threadIdx.x;
   double* x = M + (int64_t)col * ld;
   double s = 0.0;
-  for (int i = k + 1 + tid; i < m; i += 256) s = fma(x[i], x[i], s);
+  for (int i = k + 1 + tid; i < m; i += NT) s = fma(x[i], x[i], s);
   const double sigma = wg_sum(s, red);
   const double x0 = x[k];
   double tau = 0.0, beta = x0, scale = 0.0;
@@ -109,7 +128,7 @@ __device__ double house(double* __restrict__ M, int64_t ld, int m, int k, int co
   }
   __syncthreads();  // every thread has read x0
   if (sigma > 0.0)
-    for (int i = k + 1 + tid; i < m; i += 256) x[i] *= scale;
+    for (int i = k + 1 + tid; i < m; i += NT) x[i] *= scale;
   if (tid == 0) x[k] = beta;
   __syncthreads();
   return tau;
@@ -122,7 +141,7 @@ __device__ void apply_house(double* __restrict__ M, int64_t ld, int m, int k, in
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const double* v = M + (int64_t)vc * ld;
   // one wave per column: dot, then update
-  for (int j = c0 + w; j < c1; j += 4) {
+  for (int j = c0 + w; j < c1; j += NWV) {
     double* y = M + (int64_t)j * ld;
     double s = 0.0;
     for (int i = k + lane; i < m; i += 64) s = fma(i == k ? 1.0 : v[i], y[i], s);
@@ -138,9 +157,9 @@ __device__ void apply_house(double* __restrict__ M, int64_t ld, int m, int k, in
 // ---------------------------------------------------------------------- QR
 // In place: A (m x n) -> R in the upper triangle, reflectors below.  Writes
 // the explicit Q (m x r, r = min(m, n)) and |R_jj| (r values).
-__global__ void __launch_bounds__(256) bqr_kernel(const sk_qr_desc* __restrict__ descs) {
-  const sk_qr_desc g = descs[blockIdx.x];
-  __shared__ double red[4];
+__global__ void __launch_bounds__(NT) bqr_kernel(const DescPack<sk_qr_desc, CAP_QR> pk) {
+  const sk_qr_desc g = pk.d[blockIdx.x];
+  __shared__ double red[NWV];
   __shared__ double taus[1024];
   const int m = g.m, n = g.n, r = min(m, n);
   const int tid = threadIdx.x;
@@ -150,10 +169,10 @@ __global__ void __launch_bounds__(256) bqr_kernel(const sk_qr_desc* __restrict__
     apply_house(g.A, g.lda, m, k, k, tau, k + 1, n, red);
   }
   __syncthreads();
-  for (int k = tid; k < r; k += 256) g.rdiag[k] = fabs(g.A[k + (int64_t)k * g.lda]);
+  for (int k = tid; k < r; k += NT) g.rdiag[k] = fabs(g.A[k + (int64_t)k * g.lda]);
   if (!g.Q) return;
   // Q = H_0 ... H_{r-1} [I; 0], accumulated backwards
-  for (int e = tid; e < m * r; e += 256) {
+  for (int e = tid; e < m * r; e += NT) {
     const int i = e % m, j = e / m;
     g.Q[i + (int64_t)j * g.ldq] = i == j ? 1.0 : 0.0;
   }
@@ -163,7 +182,7 @@ __global__ void __launch_bounds__(256) bqr_kernel(const sk_qr_desc* __restrict__
     if (tau == 0.0) continue;
     const double* v = g.A + (int64_t)k * g.lda;
     const int lane = tid & 63, w = tid >> 6;
-    for (int j = k + w; j < r; j += 4) {
+    for (int j = k + w; j < r; j += NWV) {
       double* y = g.Q + (int64_t)j * g.ldq;
       double s = 0.0;
       for (int i = k + lane; i < m; i += 64) s = fma(i == k ? 1.0 : v[i], y[i], s);
@@ -182,17 +201,17 @@ __global__ void __launch_bounds__(256) bqr_kernel(const sk_qr_desc* __restrict__
 // norm; stop at the first k with norm < max(eps_a, eps_r * |R_00|).  Writes the
 // rank k, the permutation (perm[0:k] the selected columns) and
 // Y = [I, R11^{-1} R12] P^T (k x q, column j of Y for column j of M).
-__global__ void __launch_bounds__(256) bid_kernel(const sk_id_desc* __restrict__ descs) {
-  const sk_id_desc g = descs[blockIdx.x];
-  __shared__ double red[4];
-  __shared__ double bestv[4];
-  __shared__ int besti[4];
+__global__ void __launch_bounds__(NT) bid_kernel(const DescPack<sk_id_desc, CAP_ID> pk) {
+  const sk_id_desc g = pk.d[blockIdx.x];
+  __shared__ double red[NWV];
+  __shared__ double bestv[NWV];
+  __shared__ int besti[NWV];
   __shared__ int s_piv;
   __shared__ double s_nk;
   const int p = g.p, q = g.q, r = min(p, q);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double* M = g.M;
-  for (int j = tid; j < q; j += 256) g.perm[j] = j;
+  for (int j = tid; j < q; j += NT) g.perm[j] = j;
   __syncthreads();
   int rank = 0;
   double r00 = -1.0;
@@ -200,7 +219,7 @@ __global__ void __launch_bounds__(256) bid_kernel(const sk_id_desc* __restrict__
     // exact norms of the trailing columns, one wave per column; best = first max
     double bv = -1.0;
     int bi = q;
-    for (int j = k + w; j < q; j += 4) {
+    for (int j = k + w; j < q; j += NWV) {
       const double* y = M + (int64_t)j * g.ldm;
       double s = 0.0;
       for (int i = k + lane; i < p; i += 64) s = fma(y[i], y[i], s);
@@ -220,7 +239,7 @@ __global__ void __launch_bounds__(256) bid_kernel(const sk_id_desc* __restrict__
     if (tid == 0) {
       double b = -1.0;
       int bj = q;
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < NWV; ++u)
         if (bestv[u] > b || (bestv[u] == b && besti[u] < bj)) {
           b = bestv[u];
           bj = besti[u];
@@ -236,7 +255,7 @@ __global__ void __launch_bounds__(256) bid_kernel(const sk_id_desc* __restrict__
     if (piv != k) {  // swap columns k and piv
       double* a = M + (int64_t)k * g.ldm;
       double* b = M + (int64_t)piv * g.ldm;
-      for (int i = tid; i < p; i += 256) {
+      for (int i = tid; i < p; i += NT) {
         const double t = a[i];
         a[i] = b[i];
         b[i] = t;
@@ -255,10 +274,10 @@ __global__ void __launch_bounds__(256) bid_kernel(const sk_id_desc* __restrict__
   if (tid == 0) *g.rank = rank;
   // Y (k x q): identity on the selected columns, X = R11^{-1} R12 on the rest,
   // by back substitution, one thread per column of R12
-  for (int e = tid; e < rank * q; e += 256) g.Y[(e % rank) + (int64_t)(e / rank) * g.ldy] = 0.0;
+  for (int e = tid; e < rank * q; e += NT) g.Y[(e % rank) + (int64_t)(e / rank) * g.ldy] = 0.0;
   __syncthreads();
-  for (int j = tid; j < rank; j += 256) g.Y[j + (int64_t)g.perm[j] * g.ldy] = 1.0;
-  for (int c = rank + tid; c < q; c += 256) {
+  for (int j = tid; j < rank; j += NT) g.Y[j + (int64_t)g.perm[j] * g.ldy] = 1.0;
+  for (int c = rank + tid; c < q; c += NT) {
     double* y = g.Y + (int64_t)g.perm[c] * g.ldy;
     const double* rc = M + (int64_t)c * g.ldm;
     for (int i = rank - 1; i >= 0; --i) {
@@ -270,12 +289,12 @@ __global__ void __launch_bounds__(256) bid_kernel(const sk_id_desc* __restrict__
 }
 
 // ----------------------------------------------------------- norms, gathers
-__global__ void __launch_bounds__(256) bnorm_kernel(const sk_norm_desc* __restrict__ descs) {
-  const sk_norm_desc g = descs[blockIdx.x];
-  __shared__ double red[4];
+__global__ void __launch_bounds__(NT) bnorm_kernel(const DescPack<sk_norm_desc, CAP_NORM> pk) {
+  const sk_norm_desc g = pk.d[blockIdx.x];
+  __shared__ double red[NWV];
   double s = 0.0;
   const int64_t tot = (int64_t)g.m * g.n;
-  for (int64_t e = threadIdx.x; e < tot; e += 256) {
+  for (int64_t e = threadIdx.x; e < tot; e += NT) {
     const double v = g.A[(e % g.m) + (e / g.m) * g.lda];
     s = fma(v, v, s);
   }
@@ -284,8 +303,8 @@ __global__ void __launch_bounds__(256) bnorm_kernel(const sk_norm_desc* __restri
 }
 
 // dst(i, j) = src(rows[i], cols[j]) (rows / cols NULL: row0 + i / col0 + j)
-__global__ void __launch_bounds__(256) bgather_kernel(const sk_gather_desc* __restrict__ descs) {
-  const sk_gather_desc g = descs[blockIdx.y];
+__global__ void __launch_bounds__(256) bgather_kernel(const DescPack<sk_gather_desc, CAP_GATHER> pk) {
+  const sk_gather_desc g = pk.d[blockIdx.y];
   const int64_t tot = (int64_t)g.m * g.n;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
     const int i = (int)(e % g.m), j = (int)(e / g.m);
@@ -342,26 +361,13 @@ __global__ void __launch_bounds__(256) rrows_kernel(RRowsArgs a, int bsel) {
   }
 }
 
-// descriptors of a batched call: copied into a grow-only device buffer of the
-// context (one batched call at a time per context, as every compute call)
-template <typename D>
-static int upload_descs(Ctx* c, const D* descs, int count, hipStream_t st, const D** dev) {
-  const size_t bytes = sizeof(D) * (size_t)count;
-  if (bytes > c->desc_bytes) {
-    if (c->desc_buf) {
-      SK_HIP(hipFree(c->desc_buf));  // (synchronises: no earlier launch still reads it)
-      c->desc_buf = nullptr;
-      c->desc_bytes = 0;
-    }
-    const size_t cap = std::max<size_t>(bytes, 64 << 10);
-    if (int rc = ctx_malloc(c, &c->desc_buf, cap)) return rc;
-    c->desc_bytes = cap;
-  }
-  // the host array may be reused once this returns: copy synchronously on st
-  SK_HIP(hipMemcpyAsync(c->desc_buf, descs, bytes, hipMemcpyHostToDevice, st));
-  SK_HIP(hipStreamSynchronize(st));
-  *dev = (const D*)c->desc_buf;
-  return SK_OK;
+// copy descriptors [b0, b0 + n) of a call into a launch's pack
+template <typename D, int CAP>
+static DescPack<D, CAP> pack(const D* descs, int b0, int n) {
+  DescPack<D, CAP> pk;
+  memset(&pk, 0, sizeof(pk));
+  memcpy(pk.d, descs + b0, sizeof(D) * (size_t)n);
+  return pk;
 }
 
 }  // namespace sk
@@ -379,7 +385,6 @@ int sketch_batched_gemm(sk_ctx* ctx, const sk_gemm_desc* descs, int32_t count, v
   if (int rc = check_live(ctx)) return rc;
   SK_REQUIRE(count >= 0 && (count == 0 || descs), SK_EINVAL, "bad descriptor array");
   if (count == 0) return SK_OK;
-  int tiles = 1;
   for (int b = 0; b < count; ++b) {
     const sk_gemm_desc& g = descs[b];
     SK_REQUIRE(g.m >= 0 && g.n >= 0 && g.k >= 0, SK_EINVAL, "gemm %d: negative size", b);
@@ -388,16 +393,18 @@ int sketch_batched_gemm(sk_ctx* ctx, const sk_gemm_desc* descs, int32_t count, v
     SK_REQUIRE(g.ldc >= std::max(1, g.m), SK_EINVAL, "gemm %d: ldc < m", b);
     SK_REQUIRE(g.lda >= std::max(1, g.transA ? g.k : g.m), SK_EINVAL, "gemm %d: lda too small", b);
     SK_REQUIRE(g.ldb >= std::max(1, g.transB ? g.n : g.k), SK_EINVAL, "gemm %d: ldb too small", b);
-    tiles = std::max(tiles, ((g.m + GT - 1) / GT) * ((g.n + GT - 1) / GT));
   }
-  SK_REQUIRE(count <= 65535, SK_EINVAL, "at most 65535 descriptors per call");
   SK_HIP(hipSetDevice(ctx->c.device));
   hipStream_t st = (hipStream_t)stream;
-  const sk_gemm_desc* dev = nullptr;
-  if (int rc = upload_descs(&ctx->c, descs, count, st, &dev)) return rc;
   ProfScope ps(&ctx->c, "hss_gemm", st);
-  bgemm_kernel<<<dim3((unsigned)tiles, 1, (unsigned)count), 256, 0, st>>>(dev);
-  SK_HIP(hipGetLastError());
+  for (int b0 = 0; b0 < count; b0 += CAP_GEMM) {
+    const int n = std::min(CAP_GEMM, count - b0);
+    int tl = 1;
+    for (int b = b0; b < b0 + n; ++b)
+      tl = std::max(tl, ((descs[b].m + GT - 1) / GT) * ((descs[b].n + GT - 1) / GT));
+    bgemm_kernel<<<dim3((unsigned)tl, 1, (unsigned)n), 256, 0, st>>>(pack<sk_gemm_desc, CAP_GEMM>(descs, b0, n));
+    SK_HIP(hipGetLastError());
+  }
   return SK_OK;
 }
 
@@ -413,11 +420,12 @@ int sketch_batched_qr(sk_ctx* ctx, const sk_qr_desc* descs, int32_t count, void*
   }
   SK_HIP(hipSetDevice(ctx->c.device));
   hipStream_t st = (hipStream_t)stream;
-  const sk_qr_desc* dev = nullptr;
-  if (int rc = upload_descs(&ctx->c, descs, count, st, &dev)) return rc;
   ProfScope ps(&ctx->c, "hss_qr", st);
-  bqr_kernel<<<(unsigned)count, 256, 0, st>>>(dev);
-  SK_HIP(hipGetLastError());
+  for (int b0 = 0; b0 < count; b0 += CAP_QR) {
+    const int n = std::min(CAP_QR, count - b0);
+    bqr_kernel<<<(unsigned)n, NT, 0, st>>>(pack<sk_qr_desc, CAP_QR>(descs, b0, n));
+    SK_HIP(hipGetLastError());
+  }
   return SK_OK;
 }
 
@@ -433,11 +441,12 @@ int sketch_batched_id(sk_ctx* ctx, const sk_id_desc* descs, int32_t count, void*
   }
   SK_HIP(hipSetDevice(ctx->c.device));
   hipStream_t st = (hipStream_t)stream;
-  const sk_id_desc* dev = nullptr;
-  if (int rc = upload_descs(&ctx->c, descs, count, st, &dev)) return rc;
   ProfScope ps(&ctx->c, "hss_id", st);
-  bid_kernel<<<(unsigned)count, 256, 0, st>>>(dev);
-  SK_HIP(hipGetLastError());
+  for (int b0 = 0; b0 < count; b0 += CAP_ID) {
+    const int n = std::min(CAP_ID, count - b0);
+    bid_kernel<<<(unsigned)n, NT, 0, st>>>(pack<sk_id_desc, CAP_ID>(descs, b0, n));
+    SK_HIP(hipGetLastError());
+  }
   return SK_OK;
 }
 
@@ -452,11 +461,12 @@ int sketch_batched_norm(sk_ctx* ctx, const sk_norm_desc* descs, int32_t count, v
   }
   SK_HIP(hipSetDevice(ctx->c.device));
   hipStream_t st = (hipStream_t)stream;
-  const sk_norm_desc* dev = nullptr;
-  if (int rc = upload_descs(&ctx->c, descs, count, st, &dev)) return rc;
   ProfScope ps(&ctx->c, "hss_norm", st);
-  bnorm_kernel<<<(unsigned)count, 256, 0, st>>>(dev);
-  SK_HIP(hipGetLastError());
+  for (int b0 = 0; b0 < count; b0 += CAP_NORM) {
+    const int n = std::min(CAP_NORM, count - b0);
+    bnorm_kernel<<<(unsigned)n, NT, 0, st>>>(pack<sk_norm_desc, CAP_NORM>(descs, b0, n));
+    SK_HIP(hipGetLastError());
+  }
   return SK_OK;
 }
 
@@ -464,23 +474,23 @@ int sketch_batched_gather(sk_ctx* ctx, const sk_gather_desc* descs, int32_t coun
   if (int rc = check_live(ctx)) return rc;
   SK_REQUIRE(count >= 0 && (count == 0 || descs), SK_EINVAL, "bad descriptor array");
   if (count == 0) return SK_OK;
-  int64_t most = 1;
   for (int b = 0; b < count; ++b) {
     const sk_gather_desc& g = descs[b];
     SK_REQUIRE(g.m >= 0 && g.n >= 0, SK_EINVAL, "gather %d: negative size", b);
     SK_REQUIRE((int64_t)g.m * g.n == 0 || (g.src && g.dst), SK_EINVAL, "gather %d: NULL pointer", b);
     SK_REQUIRE(g.ldd >= std::max(1, g.m), SK_EINVAL, "gather %d: ldd < m", b);
-    most = std::max<int64_t>(most, (int64_t)g.m * g.n);
   }
-  SK_REQUIRE(count <= 65535, SK_EINVAL, "at most 65535 descriptors per call");
   SK_HIP(hipSetDevice(ctx->c.device));
   hipStream_t st = (hipStream_t)stream;
-  const sk_gather_desc* dev = nullptr;
-  if (int rc = upload_descs(&ctx->c, descs, count, st, &dev)) return rc;
   ProfScope ps(&ctx->c, "hss_gather", st);
-  const unsigned gx = (unsigned)std::min<int64_t>((most + 255) / 256, 1024);
-  bgather_kernel<<<dim3(gx, (unsigned)count), 256, 0, st>>>(dev);
-  SK_HIP(hipGetLastError());
+  for (int b0 = 0; b0 < count; b0 += CAP_GATHER) {
+    const int n = std::min(CAP_GATHER, count - b0);
+    int64_t mx = 1;
+    for (int b = b0; b < b0 + n; ++b) mx = std::max<int64_t>(mx, (int64_t)descs[b].m * descs[b].n);
+    const unsigned gx = (unsigned)std::min<int64_t>((mx + 255) / 256, 1024);
+    bgather_kernel<<<dim3(gx, (unsigned)n), 256, 0, st>>>(pack<sk_gather_desc, CAP_GATHER>(descs, b0, n));
+    SK_HIP(hipGetLastError());
+  }
   return SK_OK;
 }
 

@@ -80,9 +80,6 @@ struct Ctx {
   void* fixed_work = nullptr;
   size_t fixed_bytes = 0;
   bool use_fixed = false;
-  // descriptor arrays of the batched per-node kernels (grow-only)
-  void* desc_buf = nullptr;
-  size_t desc_bytes = 0;
 };
 
 // the workspace the kernels write (valid after a successful ensure_work)

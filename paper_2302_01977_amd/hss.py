@@ -204,6 +204,7 @@ class _Compressor:
         self.batch = _Batch(ctx)
         self.lib = abi.load()
         self._keep = []     # temporaries of the launches in flight (device index arrays, work buffers)
+        self._pend = []     # copies of grown buffers not yet issued
         # Algorithm 1: R <- JL-Operator(d0 + dd, n), here a block of d0 columns
         # and one of dd; S <- A R (and S' <- A^T R)
         self.sk = Sketch(ctx, A, kind, d0, seed, alpha=alpha, transpose=not symmetric)
@@ -230,17 +231,26 @@ class _Compressor:
 
     def _grow(self, buf, rows, width, keep):
         """A buffer of at least ``width`` columns holding the first ``keep``
-        columns of ``buf`` (capacity doubles)."""
+        columns of ``buf`` (capacity doubles); the copy joins the pending ones,
+        which ``_flush`` issues in one batched launch."""
         if buf is not None and buf.shape[1] >= width:
             return buf
         cap = max(width, 2 * (buf.shape[1] if buf is not None else 0))
         nb = _f64(rows, cap)
         if buf is not None and keep and rows:
-            self.batch.gather([_copy((nb, 0, 0), (buf, 0, 0), rows, keep)])
+            self._pend.append(_copy((nb, 0, 0), (buf, 0, 0), rows, keep))
+            self._keep.append(buf)
         return nb
 
+    def _flush(self):
+        self.batch.gather(self._pend)
+        self._pend = []
+
     def _idx(self, a):
-        return torch.as_tensor(np.asarray(a, dtype=np.int64)).cuda()
+        """Device copy of an index list (pinned staging, no wait for the device)."""
+        t = torch.as_tensor(np.asarray(a, dtype=np.int64)).pin_memory().cuda(non_blocking=True)
+        self._keep.append(t)
+        return t
 
     # ------------------------------------------------------------- sweep
     def run(self):
@@ -363,6 +373,7 @@ class _Compressor:
                             gem.append(_gemm((buf, r0, i0), (B, 0, 0), (Rl, 0, i0), k, w, kk,
                                              alpha=-1.0, beta=1.0, ta=tb))
                     r0 += k
+        self._flush()  # old columns of grown buffers (disjoint from the new ones written here)
         self.batch.gather(gat)
         self.batch.gemm(gem)
 
@@ -396,6 +407,7 @@ class _Compressor:
                 nq = t.nq if side == "S" else t.nqt
                 p[side + "_Q"] = self._grow(t.Q if side == "S" else t.Qt, m, nq + dd, nq)
                 p[side + "_nq"] = nq
+        self._flush()
         self.batch.gather(gat)
         self.batch.qr(qrs)
         self.batch.gather(r00)
@@ -481,8 +493,9 @@ class _Compressor:
             return
         sides = [(p, side) for p in newly for side in self._sides()]
         qtot = sum((p["t"].m if s == "S" else p["t"].mt) for p, s in sides)
-        perm = torch.zeros(max(1, qtot), dtype=torch.int32, device="cuda")
-        rank = torch.zeros(len(sides), dtype=torch.int32, device="cuda")
+        # ranks, then the permutations: one read-back
+        iw = torch.zeros(len(sides) + max(1, qtot), dtype=torch.int32, device="cuda")
+        rank, perm = iw[:len(sides)], iw[len(sides):]
         gat, ids, offs = [], [], []
         o = 0
         for q, (p, side) in enumerate(sides):
@@ -501,7 +514,8 @@ class _Compressor:
             o += m
         self.batch.gather(gat)
         self.batch.ident(ids)
-        pv, rv = perm.cpu().numpy(), rank.cpu().numpy()
+        iv = iw.cpu().numpy()
+        rv, pv = iv[:len(sides)], iv[len(sides):]
         for q, (p, side) in enumerate(sides):
             t = p["t"]
             a, m, Y = offs[q]
@@ -572,6 +586,7 @@ class _Compressor:
                 c1, c2 = t.children
                 t.Itil = np.concatenate([c1.Itil, c2.Itil])[t.J]
                 t.Itilt = np.concatenate([c1.Itilt, c2.Itilt])[t.Jt]
+        self._flush()
         # two products into one Rl column block (k1 then k2 with beta = 1) must
         # not run concurrently: split them over two launches
         first, second = [], []
