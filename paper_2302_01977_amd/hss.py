@@ -246,11 +246,26 @@ class _Compressor:
         self.batch.gather(self._pend)
         self._pend = []
 
-    def _idx(self, a):
-        """Device copy of an index list (pinned staging, no wait for the device)."""
-        t = torch.as_tensor(np.asarray(a, dtype=np.int64)).pin_memory().cuda(non_blocking=True)
-        self._keep.append(t)
-        return t
+    def _stage(self, reqs):
+        """Index lists of one phase in one upload: ``reqs`` holds (descriptor,
+        field, host array); the arrays go through one pinned buffer and one
+        asynchronous copy, and each descriptor field receives its device
+        pointer."""
+        if not reqs:
+            return
+        tot = sum(len(a) for _, _, a in reqs)
+        host = torch.empty(max(tot, 1), dtype=torch.int64, pin_memory=True)
+        hv = host.numpy()
+        offs, o = [], 0
+        for _, _, a in reqs:
+            hv[o:o + len(a)] = a
+            offs.append(o)
+            o += len(a)
+        dev = host.to("cuda", non_blocking=True)
+        self._keep += [host, dev]
+        base = dev.data_ptr()
+        for (desc, field, _), off in zip(reqs, offs):
+            setattr(desc, field, base + 8 * off)
 
     # ------------------------------------------------------------- sweep
     def run(self):
@@ -279,20 +294,20 @@ class _Compressor:
 
     def _couplings(self, nodes):
         """B12 = A(I~_1, I~'_2) and B21 = A(I~_2, I~'_1) of the untouched internal nodes."""
-        gat = []
+        gat, reqs = [], []
         for t in nodes:
             if t.state == UNTOUCHED and not t.is_leaf:
                 c1, c2 = t.children
                 bl = []
                 for (ra, ca) in ((c1.Itil, c2.Itilt), (c2.Itil, c1.Itilt)):
                     B = _f64(len(ra), len(ca))
-                    ri, ci = self._idx(ra), self._idx(ca)
                     bl.append(B)
-                    self._keep += [ri, ci]
-                    gat.append(abi.SkGatherDesc(m=len(ra), n=len(ca), trans=0, src=self.A.data_ptr(),
-                                                lds=_ld(self.A), rows=ri.data_ptr(), cols=ci.data_ptr(), row0=0,
-                                                col0=0, dst=B.data_ptr(), ldd=_ld(B)))
+                    g = abi.SkGatherDesc(m=len(ra), n=len(ca), trans=0, src=self.A.data_ptr(), lds=_ld(self.A),
+                                         rows=None, cols=None, row0=0, col0=0, dst=B.data_ptr(), ldd=_ld(B))
+                    reqs += [(g, "rows", ra), (g, "cols", ca)]
+                    gat.append(g)
                 t.B12, t.B21 = bl
+        self._stage(reqs)
         self.batch.gather(gat)
 
     def _sides(self):
@@ -334,7 +349,7 @@ class _Compressor:
         the skeleton rows of the children's local sketches, minus the diagonal
         block times R (leaf) or the couplings times the children's local
         operators (internal node)."""
-        gat, gem = [], []
+        gat, gem, reqs = [], [], []
         for p in plan:
             t, i0 = p["t"], p["i0"]
             w = i1 - i0
@@ -364,16 +379,16 @@ class _Compressor:
                 for (J, cS, B, Rl, kk, tb) in parts:
                     k = len(J)
                     if k:
-                        ji = self._idx(J)
-                        self._keep.append(ji)
-                        gat.append(abi.SkGatherDesc(m=k, n=w, trans=0, src=cS.data_ptr(), lds=_ld(cS),
-                                                    rows=ji.data_ptr(), cols=None, row0=0, col0=i0,
-                                                    dst=_ptr(buf, r0, i0), ldd=_ld(buf)))
+                        gd = abi.SkGatherDesc(m=k, n=w, trans=0, src=cS.data_ptr(), lds=_ld(cS), rows=None,
+                                              cols=None, row0=0, col0=i0, dst=_ptr(buf, r0, i0), ldd=_ld(buf))
+                        reqs.append((gd, "rows", J))
+                        gat.append(gd)
                         if kk:
                             gem.append(_gemm((buf, r0, i0), (B, 0, 0), (Rl, 0, i0), k, w, kk,
                                              alpha=-1.0, beta=1.0, ta=tb))
                     r0 += k
         self._flush()  # old columns of grown buffers (disjoint from the new ones written here)
+        self._stage(reqs)
         self.batch.gather(gat)
         self.batch.gemm(gem)
 
