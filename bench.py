@@ -48,8 +48,8 @@ GATHER_SOURCES = ("paper_2302_01977_amd/csrc/sjlt.hip", "paper_2302_01977_amd/cs
 # rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of the step's two kernels (S, S')
 TRAFFIC_FILES = {"sjlt_gather": os.path.join(ROOT, "profiles", "sjlt_gather_S_cauchy16k_traffic.txt"),
                  "sjlt_gather_t": os.path.join(ROOT, "profiles", "sjlt_gather_St_cauchy16k_traffic.txt")}
-STEP_KERNELS = {"sjlt_gather": "sjlt_gather_kernel<double, false, 16, 16, 1, 256, true> (S = A R)",
-                "sjlt_gather_t": "sjlt_gather_kernel<double, true, 16, 16, 1, 256, true> (S' = A^T R)"}
+STEP_KERNELS = {"sjlt_gather": "sjlt_gather_kernel<double, false, 16, 16, 1, 256, true, false> (S = A R)",
+                "sjlt_gather_t": "sjlt_gather_kernel<double, true, 16, 16, 1, 256, true, false> (S' = A^T R)"}
 
 
 def parse():
