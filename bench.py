@@ -263,10 +263,10 @@ def rel_err(x, ref):
     return float(torch.linalg.norm((x.double() - ref.double())) / torch.linalg.norm(ref.double()))
 
 
-def stored_leg(api, ctx, A, kind, d, seed, alpha, prec, steps, warmup, bytes_step):
+def stored_leg(api, ctx, A, kind, d, seed, alpha, prec, steps, warmup, bytes_step, construction="block"):
     import torch
     try:
-        sk = api.Sketch(ctx, A, kind, d, seed, alpha=alpha, prec=prec, transpose=True)
+        sk = api.Sketch(ctx, A, kind, d, seed, alpha=alpha, prec=prec, transpose=True, construction=construction)
     except api.SketchError as e:
         return {"unavailable": str(e)}, None
     ms = time_steps(lambda i: sk.rerun(seed + i), steps, warmup)
@@ -361,6 +361,11 @@ def hss_device_leg(api, ctx, A16=None, reps=3):
     if A16 is None:
         A16 = api.to_device_colmajor(workloads.cfg2()["A"])
     out["cauchy16k_sjlt"] = run(A16, "sjlt", workloads.OP_SEED[2], 256, 64, 64, 1e-8, 1e-8, False)
+    # the QChem Toeplitz matrix of section 8.1 (n = 1000, spacing 0.1) with SRHT
+    # (n not a power of two) and with the SJLT graph construction
+    T = api.to_device_colmajor(workloads.qchem_toeplitz_dense(1000, 0.1))
+    out["toeplitz1000_srht"] = run(T, "srht", 91, 64, 64, 64, 1e-6, 1e-8, True)
+    out["workload"] += "; QChem Toeplitz n=1000 (spacing 0.1, leaf 64, d0=dd=64, eps 1e-6) with SRHT"
     return out
 
 
@@ -620,6 +625,22 @@ def main():
         results[kind] = r
         if sk is not None:
             sketches[kind] = sk
+    if args.leg == "all":
+        # the SJLT graph construction (alpha distinct positions per row) on the
+        # same matrix, and the SRHT for a size that is not a power of two (the
+        # leading 15000 x 15000 block of A, nu = 16384: zero-padded chunks)
+        r, sk = stored_leg(api, ctx, A, "sjlt", d, seed, alpha, "native", args.steps, args.warmup, step_bytes(8),
+                           construction="graph")
+        results["sjlt_graph"] = r
+        if sk is not None:
+            sk.release()
+        n2 = 15000
+        r, sk = stored_leg(api, ctx, A[:n2, :n2], "srht", d, seed, alpha, "native", args.steps, args.warmup,
+                           2 * (n2 * n2 * 8 + n2 * d * 8))
+        r["n"], r["nu"] = n2, 16384
+        results["srht_n15000"] = r
+        if sk is not None:
+            sk.release()
 
     if args.leg in ("all", "fp32"):
         # library FP64 GEMM (rocBLAS through torch) on the same shapes, for the
