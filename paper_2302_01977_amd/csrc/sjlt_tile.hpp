@@ -25,6 +25,7 @@
 // then free of bank conflicts.
 #pragma once
 #include <algorithm>
+#include <type_traits>
 
 #include "gather.hpp"
 #include "internal.hpp"
@@ -167,10 +168,11 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
       }
     }
   };
-  auto load_chunk = [&](int t) {
+  // FULL: every chunk of the tile is known to lie inside A
+  auto load_chunk = [&](int t, auto fullc) __attribute__((always_inline)) {
     load_meta(t);
     const int64_t k0 = (int64_t)t * KCK;
-    const bool full = l0 + TL <= L && k0 + KCK <= K;  // uniform
+    const bool full = decltype(fullc)::value || (l0 + TL <= L && k0 + KCK <= K);  // uniform
     if (full) {
       int64_t gr, gc;
       vec_rc(0, gr, gc, k0);
@@ -286,19 +288,33 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
     return *(const VT*)(tbase + a);
   };
 
-  if (t0 < t1) load_chunk(t0);
-  for (int t = t0; t < t1; ++t) {
-    __syncthreads();  // the previous chunk is fully consumed
-    store_chunk();
-    __syncthreads();
-    if (t + 1 < t1) load_chunk(t + 1);  // in flight during the gather below
-    if (active) {
-      if constexpr (LDSE)
-        gather_chunk_lds<T, NJ, RPL, VT, PACK, NEG>(ents, (t - blk) * kcap, bnd, bndN, lane_part, zaddr, ms, acc);
-      else
-        gather_chunk<T, NJ, RPL, VT>(ptr + (int64_t)t * prow, ent, LD, acc);
+  // FP64 one-word entries, one row per lane: the entry-window gather
+  constexpr bool WIN = PACK && RPL == 1 && NJ <= 16;
+  auto run = [&](auto fullc) __attribute__((always_inline)) {
+    if (t0 < t1) load_chunk(t0, fullc);
+    for (int t = t0; t < t1; ++t) {
+      __syncthreads();  // the previous chunk is fully consumed
+      store_chunk();
+      __syncthreads();
+      if (t + 1 < t1) load_chunk(t + 1, fullc);  // in flight during the gather below
+      if (active) {
+        if constexpr (LDSE && WIN)
+          gather_chunk_lds_win<NJ>(ents, (t - blk) * kcap, bnd, bndN, lane_part, zaddr, acc);
+        else if constexpr (LDSE)
+          gather_chunk_lds<T, NJ, RPL, VT, PACK, NEG>(ents, (t - blk) * kcap, bnd, bndN, lane_part, zaddr, ms, acc);
+        else
+          gather_chunk<T, NJ, RPL, VT>(ptr + (int64_t)t * prow, ent, LD, acc);
+      }
     }
-  }
+  };
+  // S': when no chunk of the tile reaches past A, a loop without the
+  // bounds-checked staging.  With both staging forms in one loop the compiler
+  // merges their registers after the load and waits there for the loads of
+  // the next chunk, so they would not overlap the gather.
+  if (TRANS && l0 + TL <= L && (int64_t)t1 * KCK <= K)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
 
   if (!active) return;
   const int64_t row0 = l0 + lane_elem;
