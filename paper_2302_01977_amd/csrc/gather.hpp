@@ -323,75 +323,83 @@ __device__ __forceinline__ void gather_chunk_e32_rpl(const uint32_t* E, int ebas
   }
 }
 
-// Bucket gather for one-word FP64 entries (address with the sign in bit 31),
-// one row per lane.  The wave first reads the bucket of each of its NJ
+// Bucket gather for one-word entries: the LDS address of the source row with
+// the sign in bit 31 (SGN; FP64 one row per lane, FP32 RPL rows), or, for FP32
+// with negated tile rows (!SGN), the address of the source row or of its
+// negated copy.  The wave first reads the bucket of each of a group of PG
 // columns into a VGPR window (lane k holds the bucket's entry k, lanes past the
-// end the null entry, i.e. the zero row), all NJ windows before any value:
-// a slot is then a v_readlane of a uniform word, and the value reads of all
-// columns depend on no further LDS read, so they overlap across columns
-// (gather_chunk_lds reads the entries of a column right before its values,
-// one dependent pair of LDS round trips per column).  An entry costs one LDS
-// value read; the window costs one 4-byte read per column instead of a
-// broadcast read per entry.  The sign flips the sign bit of the value read.
+// end the null entry, i.e. the zero row), all windows of the group before any
+// value: a slot is then a v_readlane of a uniform word (its sign built by
+// scalar operations), and the value reads of all columns of the group depend
+// on no further LDS read, so they overlap across columns (gather_chunk_lds
+// reads the entries of a column right before its values, one dependent pair of
+// LDS round trips per column).  An entry costs one LDS value read; a window
+// costs one 4-byte read per column instead of a broadcast read per entry.
 // Four straight-line slots per bucket, then the rest in pairs (the lane past
 // an odd end holds the null entry); buckets of more than 64 entries take more
-// windows.  The additions are those of gather_chunk_lds in the same order.
-template <int NJ>
+// windows.  The additions are those of gather_chunk_lds in the same order
+// (a + (+-1) x is exact in the product, so fma and add agree).
+template <typename T, int NJ, int RPL, typename VT, int PG, bool SGN>
 __device__ __forceinline__ void gather_chunk_lds_win(const uint32_t* E, int ebase, uint32_t bnd, uint32_t bndN,
-                                                     uint32_t lane_part, uint32_t zaddr, double (&acc)[NJ][1]) {
-  typedef __attribute__((address_space(3))) const double* lds_d;
+                                                     uint32_t lane_part, uint32_t zaddr, T (&acc)[NJ][RPL]) {
+  typedef __attribute__((address_space(3))) const VT* lds_vt;
+  static_assert(NJ % PG == 0, "whole column groups");
   const uint32_t zword = __builtin_amdgcn_readfirstlane(zaddr ^ lane_part);  // the zero row, sign +
   const int lane = (int)__lane_id();
-  // the staged value of entry word w for this lane, its sign applied:
-  // address (w & 0x7fffffff) ^ lane_part (bitop3 0x6c), then the sign bit of
-  // the value's high word XOR bit 31 of w (bitop3 0x78)
-  auto val = [&](uint32_t w) -> double {
-    const uint32_t a = __builtin_amdgcn_bitop3_b32(w, lane_part, 0x7fffffffu, 0x6c);
-    uint64_t b = __builtin_bit_cast(uint64_t, *(lds_d)(uintptr_t)a);
-    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), w, 0x80000000u, 0x78);
-    b = (b & 0xffffffffull) | ((uint64_t)hi << 32);
-    return __builtin_bit_cast(double, b);
+  // slot of the uniform entry word w: this lane's staged values, signed
+  auto slot = [&](T(&a)[RPL], uint32_t w) {
+    if constexpr (SGN) {
+      const uint32_t ad = __builtin_amdgcn_bitop3_b32(w, lane_part, 0x7fffffffu, 0x6c);  // (w & 0x7fffffff) ^ lane_part
+      const VT x = *(lds_vt)(uintptr_t)ad;
+      T sg;  // +-1 from bit 31 of w
+      if constexpr (sizeof(T) == 8)
+        sg = __builtin_bit_cast(T, (uint64_t)((w & 0x80000000u) | 0x3ff00000u) << 32);
+      else
+        sg = __builtin_bit_cast(T, (w & 0x80000000u) | 0x3f800000u);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) a[r] = fma(((const T*)&x)[r], sg, a[r]);
+    } else {
+      const VT x = *(lds_vt)(uintptr_t)(w ^ lane_part);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) a[r] += ((const T*)&x)[r];
+    }
   };
-  uint32_t win[NJ];
-  int e0s[NJ], cnts[NJ];
 #pragma unroll
-  for (int jj = 0; jj < NJ; ++jj) {
-    e0s[jj] = (int)__builtin_amdgcn_readlane(bnd, jj) - ebase;
-    const int e1 = (jj + 1 < NJ ? (int)__builtin_amdgcn_readlane(bnd, jj + 1)
-                                : (int)__builtin_amdgcn_readfirstlane(bndN)) - ebase;
-    cnts[jj] = e1 - e0s[jj];
-    win[jj] = lane < cnts[jj] ? E[e0s[jj] + lane] : zword;
-  }
+  for (int g0 = 0; g0 < NJ; g0 += PG) {
+    uint32_t win[PG];
+    int e0s[PG], cnts[PG];
 #pragma unroll
-  for (int jj = 0; jj < NJ; ++jj) {
-    const int cnt = cnts[jj];
-    double a = acc[jj][0];
-    const double x0 = val(__builtin_amdgcn_readlane(win[jj], 0)), x1 = val(__builtin_amdgcn_readlane(win[jj], 1));
-    const double x2 = val(__builtin_amdgcn_readlane(win[jj], 2)), x3 = val(__builtin_amdgcn_readlane(win[jj], 3));
-    a += x0;
-    a += x1;
-    a += x2;
-    a += x3;
-    if (cnt > 4) {
-      const int lim = cnt < 64 ? cnt : 64;
-      for (int q = 4; q < lim; q += 2) {
-        const double y0 = val(__builtin_amdgcn_readlane(win[jj], q));
-        const double y1 = val(__builtin_amdgcn_readlane(win[jj], q + 1));
-        a += y0;
-        a += y1;
-      }
-      for (int base = 64; base < cnt; base += 64) {  // buckets of more than 64 entries
-        const int c2 = cnt - base;
-        const uint32_t w2 = lane < c2 ? E[e0s[jj] + base + lane] : zword;
-        const int l2 = c2 < 64 ? c2 : 64;
-        for (int q = 0; q < l2; q += 2) {
-          const double y0 = val(__builtin_amdgcn_readlane(w2, q)), y1 = val(__builtin_amdgcn_readlane(w2, q + 1));
-          a += y0;
-          a += y1;
+    for (int j = 0; j < PG; ++j) {
+      const int jj = g0 + j;
+      e0s[j] = (int)__builtin_amdgcn_readlane(bnd, jj) - ebase;
+      const int e1 = (jj + 1 < NJ ? (int)__builtin_amdgcn_readlane(bnd, jj + 1)
+                                  : (int)__builtin_amdgcn_readfirstlane(bndN)) - ebase;
+      cnts[j] = e1 - e0s[j];
+      win[j] = lane < cnts[j] ? E[e0s[j] + lane] : zword;
+    }
+#pragma unroll
+    for (int j = 0; j < PG; ++j) {
+      const int cnt = cnts[j];
+      T(&a)[RPL] = acc[g0 + j];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) slot(a, __builtin_amdgcn_readlane(win[j], q));
+      if (cnt > 4) {
+        const int lim = cnt < 64 ? cnt : 64;
+        for (int q = 4; q < lim; q += 2) {
+          slot(a, __builtin_amdgcn_readlane(win[j], q));
+          slot(a, __builtin_amdgcn_readlane(win[j], q + 1));
+        }
+        for (int base = 64; base < cnt; base += 64) {  // buckets of more than 64 entries
+          const int c2 = cnt - base;
+          const uint32_t w2 = lane < c2 ? E[e0s[j] + base + lane] : zword;
+          const int l2 = c2 < 64 ? c2 : 64;
+          for (int q = 0; q < l2; q += 2) {
+            slot(a, __builtin_amdgcn_readlane(w2, q));
+            slot(a, __builtin_amdgcn_readlane(w2, q + 1));
+          }
         }
       }
     }
-    acc[jj][0] = a;
   }
 }
 

@@ -43,19 +43,11 @@ __global__ void __launch_bounds__(NW * 64)
   typedef typename std::conditional<RPL == 1, float, float __attribute__((ext_vector_type(2)))>::type VT;
   static_assert(RPL == 1 || RPL == 2, "one or two points per lane");
   // dynamic LDS: the tile (slot KCK: zeros for null entries), then (LDSE) the
-  // chunk's bucket entries as (LDS address of the source row, +-1.0f)
+  // chunk's bucket entries, one word each (LDS address of the source row, the
+  // sign in bit 31; the region keeps room for two words per entry)
   extern __shared__ __attribute__((aligned(16))) char smem[];
   float* const tile = (float*)smem;
   uint32_t* const ents = (uint32_t*)(smem + (KCK + 1) * ROWB);
-  // null entries (zero row, +1.0f) in the 8 slots past the staged regions,
-  // which the straight-line slots of the last bucket may read
-  if constexpr (LDSE) {
-    if (threadIdx.x < 8) {
-      const int q = pass.nblk * pass.kcap + (int)threadIdx.x;
-      ents[q * 2] = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char*)smem + (uint32_t)KCK * ROWB;
-      ents[q * 2 + 1] = 0x3f800000u;
-    }
-  }
   constexpr int NTHR = NW * 64;
   const uint32_t tile_lds = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char*)smem;
   const int tid = threadIdx.x;
@@ -111,15 +103,11 @@ __global__ void __launch_bounds__(NW * 64)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (!eptr[h]) continue;
-      uint32_t ad[4], sg[4];
+      uint32_t ad[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        ad[q] = tile_lds + (ebuf[h][q] >> 1) * ROWB;
-        sg[q] = ((ebuf[h][q] & 1u) << 31) | 0x3f800000u;
-      }
+      for (int q = 0; q < 4; ++q) ad[q] = (tile_lds + (ebuf[h][q] >> 1) * ROWB) | (ebuf[h][q] << 31);
       const int qb = (tid + h * NTHR) * 4;
-      *(u4*)&ents[qb * 2] = u4{ad[0], sg[0], ad[1], sg[1]};
-      *(u4*)&ents[qb * 2 + 4] = u4{ad[2], sg[2], ad[3], sg[3]};
+      *(u4*)&ents[qb] = u4{ad[0], ad[1], ad[2], ad[3]};
     }
     bnd = bnd_nx;
     bndN = bndN_nx;
@@ -209,8 +197,8 @@ __global__ void __launch_bounds__(NW * 64)
     __syncthreads();
     if (active) {
       if constexpr (LDSE)
-        gather_chunk_lds<float, NJ, RPL, VT>(ents, (t - blk) * pass.kcap, bnd, bndN, lane_off, zaddr, pass.ms,
-                                             acc);
+        gather_chunk_lds_win<float, NJ, RPL, VT, (RPL == 2 ? NJ : 4), true>(ents, (t - blk) * pass.kcap, bnd, bndN,
+                                                                           lane_off, zaddr, acc);
       else
         gather_chunk<float, NJ, RPL, VT>(ptr + (int64_t)t * prow, ent, LD, acc);
     }

@@ -288,8 +288,12 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
     return *(const VT*)(tbase + a);
   };
 
-  // FP64 one-word entries, one row per lane: the entry-window gather
-  constexpr bool WIN = PACK && RPL == 1 && NJ <= 16;
+  // one-word entries (FP64 one row per lane, FP32 with negated rows): the
+  // entry-window gather, windows of WPG columns at a time (FP32: 4, whose
+  // VGPRs fit beside the RPL-row accumulators; measured faster than 16 at
+  // alpha = 8, n = 65536)
+  constexpr bool WIN = ((PACK && RPL == 1) || NEG) && NJ <= 16;
+  constexpr int WPG = PACK ? NJ : (NJ < 4 ? NJ : 4);
   auto run = [&](auto fullc) __attribute__((always_inline)) {
     if (t0 < t1) load_chunk(t0, fullc);
     for (int t = t0; t < t1; ++t) {
@@ -299,7 +303,7 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
       if (t + 1 < t1) load_chunk(t + 1, fullc);  // in flight during the gather below
       if (active) {
         if constexpr (LDSE && WIN)
-          gather_chunk_lds_win<NJ>(ents, (t - blk) * kcap, bnd, bndN, lane_part, zaddr, acc);
+          gather_chunk_lds_win<T, NJ, RPL, VT, WPG, PACK>(ents, (t - blk) * kcap, bnd, bndN, lane_part, zaddr, acc);
         else if constexpr (LDSE)
           gather_chunk_lds<T, NJ, RPL, VT, PACK, NEG>(ents, (t - blk) * kcap, bnd, bndN, lane_part, zaddr, ms, acc);
         else
