@@ -75,9 +75,9 @@ struct VecT<double, 2> {
 // eptr[2] (null when the thread stages nothing); dst points at the group's
 // first output column (leading dimension ldd), scaled by sc.
 // NEG (FP32 with staged entries): the tile also holds the negated sources in
-// rows KCK + 1 .. 2 KCK, and an entry is one word, the address of the source
-// row or of its negated copy, so the gather adds without a sign and reads one
-// word per entry instead of two (the wide passes are bound by LDS bytes).
+// rows KCK + 1 .. 2 KCK, and an entry is the address of the source row or of
+// its negated copy, so the gather adds without a sign (the wide passes are
+// bound by LDS bytes).
 template <typename T, bool TRANS, int NW, int NJ, int RPL, int KCK, bool LDSE, bool NEG = false>
 __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, int64_t L, int64_t K, int64_t l0,
                                           int t0, int t1, bool active, const int32_t* __restrict__ ptr,
@@ -96,12 +96,11 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
   typedef typename VecT<T, RPL>::type VT;
 
   // Dynamic LDS: the staged tile, whose extra source slot KCK holds zeros (the
-  // source of null entries), then (LDSE) the chunk's bucket entries: FP64 one
-  // word (the entry's LDS address in the tile, its sign in bit 31), FP32 two
-  // words (address, sign as +-1.0f).
+  // source of null entries), then (LDSE) the chunk's bucket entries, one word
+  // each: the entry's LDS address in the tile with its sign in bit 31 (PACK),
+  // or with NEG the address of the source row or of its negated copy.
   constexpr int NSLOT = NEG ? 2 * KCK + 1 : KCK + 1;
-  constexpr bool PACK = SZ == 8;
-  constexpr bool ONEW = PACK || NEG;  // one word per staged entry
+  constexpr bool PACK = !NEG;
   static_assert(!NEG || (LDSE && SZ == 4), "negated rows: FP32 with staged entries");
   extern __shared__ __attribute__((aligned(16))) char smem[];
   T* tile = (T*)smem;
@@ -121,19 +120,10 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
   uint32_t bnd = 0, bndN = 0, bnd_nx = 0, bndN_nx = 0;
   for (int e = tid; e < TL; e += NTHR) tile[KCK * TL + e] = T(0);
   // The straight-line slots of the last bucket may read up to 7 entries past
-  // the staged regions (entries epad..epad+7).  Those slots address the zero
-  // row, but the FP32 form also multiplies by the staged sign, so they hold a
-  // null entry (zero row, +1) instead of whatever the LDS held before.
+  // the staged regions (entries epad..epad+7); they hold the null entry (zero
+  // row, +) instead of whatever the LDS held before.
   if constexpr (LDSE) {
-    if (tid < 8) {
-      const uint32_t zrow = tile_lds + (uint32_t)(KCK * TL * SZ);
-      if constexpr (ONEW) {
-        ents[epad + tid] = zrow;
-      } else {
-        ents[(epad + tid) * 2] = zrow;
-        ents[(epad + tid) * 2 + 1] = 0x3f800000u;
-      }
-    }
+    if (tid < 8) ents[epad + tid] = tile_lds + (uint32_t)(KCK * TL * SZ);
   }
   // ---------------------------------------------------------------- staging
   u32x4 buf[NV];
@@ -203,7 +193,7 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         if (!eptr[h]) continue;
-        uint32_t ad[4], sg[4];
+        uint32_t ad[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const uint32_t src = ebuf[h][q] >> 1;
@@ -211,18 +201,9 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
           // KCK, always the zero row)
           const uint32_t row = NEG && (ebuf[h][q] & 1u) && src < (uint32_t)KCK ? src + KCK + 1 : src;
           ad[q] = (tile_lds + row * (uint32_t)(TL * SZ)) | (TRANS ? ((src / VECN) & 15u) * 16u : 0u);
-          sg[q] = ((ebuf[h][q] & 1u) << 31) | 0x3f800000u;
+          if constexpr (PACK) ad[q] |= ebuf[h][q] << 31;
         }
-        const int qb = q0[h];
-        if constexpr (NEG) {
-          *(u32x4*)&ents[qb] = u32x4{ad[0], ad[1], ad[2], ad[3]};
-        } else if constexpr (PACK) {
-          *(u32x4*)&ents[qb] = u32x4{ad[0] | (ebuf[h][0] << 31), ad[1] | (ebuf[h][1] << 31),
-                                     ad[2] | (ebuf[h][2] << 31), ad[3] | (ebuf[h][3] << 31)};
-        } else {
-          *(u32x4*)&ents[qb * 2] = u32x4{ad[0], sg[0], ad[1], sg[1]};
-          *(u32x4*)&ents[qb * 2 + 4] = u32x4{ad[2], sg[2], ad[3], sg[3]};
-        }
+        *(u32x4*)&ents[q0[h]] = u32x4{ad[0], ad[1], ad[2], ad[3]};
       }
       bnd = bnd_nx;
       bndN = bndN_nx;
@@ -288,12 +269,11 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
     return *(const VT*)(tbase + a);
   };
 
-  // one-word entries (FP64 one row per lane, FP32 with negated rows): the
-  // entry-window gather, windows of WPG columns at a time (FP32: 4, whose
-  // VGPRs fit beside the RPL-row accumulators; measured faster than 16 at
-  // alpha = 8, n = 65536)
-  constexpr bool WIN = ((PACK && RPL == 1) || NEG) && NJ <= 16;
-  constexpr int WPG = PACK ? NJ : (NJ < 4 ? NJ : 4);
+  // the entry-window gather, windows of WPG columns at a time: all NJ for
+  // FP64 with one row per lane, else 4, whose VGPRs fit beside the RPL-row
+  // accumulators (measured faster than 16 at alpha = 8, n = 65536)
+  constexpr bool WIN = NJ <= 16;
+  constexpr int WPG = SZ == 8 && RPL == 1 ? NJ : (NJ < 4 ? NJ : 4);
   auto run = [&](auto fullc) __attribute__((always_inline)) {
     if (t0 < t1) load_chunk(t0, fullc);
     for (int t = t0; t < t1; ++t) {
@@ -333,7 +313,7 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
 // dynamic LDS of one workgroup: the tile with its zero slot (and with neg the
 // negated rows), then the entries
 inline size_t gather_lds_bytes(int esz, int kc, int tl, bool ldse, int nblk, int kcap, bool neg = false) {
-  const size_t ew = esz == 8 || neg ? 4 : 8;
+  const size_t ew = 4;  // one word per entry
   const size_t rows = neg ? 2 * (size_t)kc + 1 : (size_t)kc + 1;
   // (+8 entries: the straight-line slots of the last bucket may read up to 7 past it)
   return rows * tl * esz + (ldse ? ((size_t)nblk * kcap + 8) * ew : 0);
