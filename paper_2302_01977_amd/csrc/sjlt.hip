@@ -180,18 +180,21 @@ static DmaShape choose_dma(int dtype, int kc, int W, int g, int nblk, int kcap) 
 // when the direct-to-LDS kernel has a shape for it (it double-buffers the tile,
 // so shorter chunks keep it in LDS), else about four (and four for FP64 from
 // 256 columns on).  S': the 1 KB column
-// chunks of the direct-to-LDS S' kernel when it applies, else (register-staged
-// kernel) about four entries per bucket in FP64, two in FP32.  kct = 0 when S'
-// shares the S tables.
+// chunks of the direct-to-LDS S' kernel when it applies (and in FP32 from 256
+// columns on, for the register-staged kernel), else (register-staged kernel)
+// about four entries per bucket in FP64, two in FP32.  kct = 0 when S' shares
+// the S tables.
 // Shape of the direct-to-LDS S' kernel: one 1 KB chunk per column (KC = 256
 // sources in FP32), NJ columns per wave; nw = 0 when it does not apply.  The
 // FP64 instances (KC = 128) were measured no faster than the register-staged
 // kernel on MI355X (w = 256) or slower (w = 64, 0.70 against 0.52 ms at
-// n = 16384), so FP64 keeps the register-staged S'.
+// n = 16384), so FP64 keeps the register-staged S'.  From 256 columns on, the
+// register-staged kernel with the same 1 KB pieces is faster in FP32 too
+// (n = 16384, w = 256: 0.369 against 0.433 ms; w = 128: 0.43 against 0.39 ms).
 static DmaShape choose_dma_t(int dtype, int kc, int W, int g, int nblk, int kcap) {
   const int esz = dtype == SK_F64 ? 8 : 4;
-  if (dtype == SK_F64 || kc * esz != 1024) return DmaShape{0, 0, 0};
-  const int nj = W >= 256 ? 16 : W >= 128 ? 8 : 4;
+  if (dtype == SK_F64 || kc * esz != 1024 || W >= 256) return DmaShape{0, 0, 0};
+  const int nj = W >= 128 ? 8 : 4;
   if (g % nj != 0 || W / nj > MAX_PASS_GROUPS) return DmaShape{0, 0, 0};
   // long buckets (more than about eight entries per chunk) gather faster in the
   // register-staged kernel (measured: w = 64, alpha = 8)
@@ -209,7 +212,7 @@ void sjlt_pick_chunks(int dtype, int d, int alpha, bool want_t, int* kc, int* kc
   // w = 256: 0.517 against 0.569 ms), and S' shares its tables
   if (dtype == SK_F64 && d >= 256) *kc = sjlt_chunk_for(d, alpha, 4);
   const int kd = dtype == SK_F64 ? 128 : 256;
-  const int kt = choose_dma_t(dtype, kd, d, d, 1, sjlt_kcap(kd, alpha, d)).nw
+  const int kt = (dtype == SK_F32 && d >= 256) || choose_dma_t(dtype, kd, d, d, 1, sjlt_kcap(kd, alpha, d)).nw
                      ? kd
                      : sjlt_chunk_for(d, alpha, dtype == SK_F64 ? 4 : 2);
   *kct = want_t && kt != *kc ? kt : 0;

@@ -381,7 +381,7 @@ int launch_sjlt_dma_t(Ctx* c, int dtype, int nw, int nj, int kc, const void* A, 
     return run_dma_t<T_, NW_, NJ_, KC_>(c, (const T_*)A, lda, L, K, pass, (T_*)out, ldo, (T_)scale, split, \
                                         (T_*)part, st);
   if (dtype == SK_F32) {
-    SK_DMAT(float, 16, 16, 256) SK_DMAT(float, 16, 8, 256) SK_DMAT(float, 16, 4, 256)
+    SK_DMAT(float, 16, 8, 256) SK_DMAT(float, 16, 4, 256)
   }
 #undef SK_DMAT
   return 1;
