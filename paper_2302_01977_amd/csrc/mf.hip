@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(NW * 64)
     __syncthreads();
     if (active) {
       if constexpr (LDSE)
-        gather_chunk_lds_win<float, NJ, RPL, VT, (RPL == 2 ? NJ : 4), true>(ents, (t - blk) * pass.kcap, bnd, bndN,
+        gather_chunk_lds_win<float, NJ, RPL, VT, 4, true, RPL == 2>(ents, (t - blk) * pass.kcap, bnd, bndN,
                                                                            lane_off, zaddr, acc);
       else
         gather_chunk<float, NJ, RPL, VT>(ptr + (int64_t)t * prow, ent, LD, acc);

@@ -269,11 +269,13 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
     return *(const VT*)(tbase + a);
   };
 
-  // the entry-window gather, windows of WPG columns at a time: all NJ for
-  // FP64 with one row per lane, else 4, whose VGPRs fit beside the RPL-row
-  // accumulators (measured faster than 16 at alpha = 8, n = 65536)
+  // the entry-window gather, windows of 4 columns at a time; FP64 with one row
+  // per lane takes the straight-line slots of the 4 columns first (n = 16384
+  // step: S 0.473 -> 0.461 ms against 16-column windows; in FP32 the value
+  // registers of the group would push the kernels past their VGPR budget)
   constexpr bool WIN = NJ <= 16;
-  constexpr int WPG = SZ == 8 && RPL == 1 ? NJ : (NJ < 4 ? NJ : 4);
+  constexpr int WPG = NJ < 4 ? NJ : 4;
+  constexpr bool WTWO = SZ == 8 && RPL == 1;
   auto run = [&](auto fullc) __attribute__((always_inline)) {
     if (t0 < t1) load_chunk(t0, fullc);
     for (int t = t0; t < t1; ++t) {
@@ -283,7 +285,7 @@ __device__ __forceinline__ void sjlt_tile(const T* __restrict__ A, int64_t lda, 
       if (t + 1 < t1) load_chunk(t + 1, fullc);  // in flight during the gather below
       if (active) {
         if constexpr (LDSE && WIN)
-          gather_chunk_lds_win<T, NJ, RPL, VT, WPG, PACK>(ents, (t - blk) * kcap, bnd, bndN, lane_part, zaddr, acc);
+          gather_chunk_lds_win<T, NJ, RPL, VT, WPG, PACK, WTWO>(ents, (t - blk) * kcap, bnd, bndN, lane_part, zaddr, acc);
         else if constexpr (LDSE)
           gather_chunk_lds<T, NJ, RPL, VT, PACK, NEG>(ents, (t - blk) * kcap, bnd, bndN, lane_part, zaddr, ms, acc);
         else
