@@ -55,8 +55,8 @@ STEP_KERNELS = {"sjlt_gather": "sjlt_gather_kernel<double, false, 16, 16, 1, 256
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--workload", default="cauchy16k", choices=["cauchy16k"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--leg", default="all",
