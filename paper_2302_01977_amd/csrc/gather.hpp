@@ -335,13 +335,13 @@ __device__ __forceinline__ void gather_chunk_e32_rpl(const uint32_t* E, int ebas
 // reads the entries of a column right before its values, one dependent pair of
 // LDS round trips per column).  An entry costs one LDS value read; a window
 // costs one 4-byte read per column instead of a broadcast read per entry.
-// Four straight-line slots per bucket, then the rest in pairs (the lane past
-// an odd end holds the null entry); with TWO the four slots of every column of
-// the group come first, so that the value reads of the group are in flight
-// together (this costs 4 PG RPL VGPRs).  Buckets of more than 64 entries (a
+// NS straight-line slots per bucket (4, or about the mean bucket length), then
+// the rest in pairs (the lane past an odd end holds the null entry); with TWO
+// the straight-line slots of every column of the group come first, so that the
+// value reads of the group are in flight together (this costs NS PG RPL VGPRs).  Buckets of more than 64 entries (a
 // chunk of more than 64 sources) take more windows.  The additions are those of gather_chunk_lds in the same order
 // (a + (+-1) x is exact in the product, so fma and add agree).
-template <typename T, int NJ, int RPL, typename VT, int PG, bool SGN, bool TWO>
+template <typename T, int NJ, int RPL, typename VT, int PG, bool SGN, bool TWO, int NS = 4>
 __device__ __forceinline__ void gather_chunk_lds_win(const uint32_t* E, int ebase, uint32_t bnd, uint32_t bndN,
                                                      uint32_t lane_part, uint32_t zaddr, T (&acc)[NJ][RPL]) {
   typedef __attribute__((address_space(3))) const VT* lds_vt;
@@ -385,7 +385,7 @@ __device__ __forceinline__ void gather_chunk_lds_win(const uint32_t* E, int ebas
 #pragma unroll
       for (int j = 0; j < PG; ++j) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) slot(acc[g0 + j], __builtin_amdgcn_readlane(win[j], q));
+        for (int q = 0; q < NS; ++q) slot(acc[g0 + j], __builtin_amdgcn_readlane(win[j], q));
       }
     }
 #pragma unroll
@@ -394,11 +394,11 @@ __device__ __forceinline__ void gather_chunk_lds_win(const uint32_t* E, int ebas
       T(&a)[RPL] = acc[g0 + j];
       if constexpr (!TWO) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) slot(a, __builtin_amdgcn_readlane(win[j], q));
+        for (int q = 0; q < NS; ++q) slot(a, __builtin_amdgcn_readlane(win[j], q));
       }
-      if (cnt > 4) {
+      if (cnt > NS) {
         const int lim = cnt < 64 ? cnt : 64;
-        for (int q = 4; q < lim; q += 2) {
+        for (int q = NS; q < lim; q += 2) {
           slot(a, __builtin_amdgcn_readlane(win[j], q));
           slot(a, __builtin_amdgcn_readlane(win[j], q + 1));
         }

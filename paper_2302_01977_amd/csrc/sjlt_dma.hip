@@ -29,11 +29,9 @@ __global__ void __launch_bounds__(NW * 64)
   // the same block as an LDS-address-space pointer (direct-to-LDS destinations)
   __attribute__((address_space(3))) char* const smem3 = (__attribute__((address_space(3))) char*)smem;
   const uint32_t lds0 = (uint32_t)(uintptr_t)smem3;
-  // entries in LDS: FP64 one word (address, sign in bit 31); FP32 two words
-  // (address, +-1.0f), which measured faster for the FP32 gather
-  constexpr bool PACK = SZ == 8;
-  constexpr int EW = PACK ? 1 : 2;
-  const int ebytes = (pass.nblk * pass.kcap + 8) * EW * 4;  // one entry buffer (+8: masked slot reads)
+  // entries in LDS: one word (address, sign in bit 31), read through entry
+  // windows (gather.hpp)
+  const int ebytes = (pass.nblk * pass.kcap + 8) * 4;  // one entry buffer (+8 spare)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -67,19 +65,6 @@ __global__ void __launch_bounds__(NW * 64)
   for (int e = tid; e < TL; e += NTHR) {
     ((T*)smem)[KCK * TL + e] = T(0);
     ((T*)(smem + TBYTES))[KCK * TL + e] = T(0);
-  }
-  // null entries (zero row, +1) in the 8 slots past each entry buffer, which
-  // the straight-line slots of the last bucket may read: the FP32 form
-  // multiplies by the staged sign
-  if (tid < 16) {
-    const int b = tid >> 3, q = pass.nblk * pass.kcap + (tid & 7);
-    const uint32_t zrow = tile_base(b) + (uint32_t)(KCK * TL * SZ);
-    if constexpr (PACK) {
-      ents_of(b)[q] = zrow;
-    } else {
-      ents_of(b)[q * 2] = zrow;
-      ents_of(b)[q * 2 + 1] = 0x3f800000u;
-    }
   }
 
   auto load_meta = [&](int t) {
@@ -122,22 +107,10 @@ __global__ void __launch_bounds__(NW * 64)
     for (int h = 0; h < 2; ++h) {
       if (!eptr[h]) continue;
       const int qb = (tid + h * NTHR) * 4;
-      if constexpr (PACK) {
-        u32x4 wd;
+      u32x4 wd;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          wd[q] = (base + (ebuf[h][q] >> 1) * (uint32_t)(TL * SZ)) | (ebuf[h][q] << 31);
-        *(u32x4*)&ents[qb] = wd;
-      } else {
-        uint32_t ad[4], sg[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          ad[q] = base + (ebuf[h][q] >> 1) * (uint32_t)(TL * SZ);
-          sg[q] = ((ebuf[h][q] & 1u) << 31) | 0x3f800000u;
-        }
-        *(u32x4*)&ents[qb * 2] = u32x4{ad[0], sg[0], ad[1], sg[1]};
-        *(u32x4*)&ents[qb * 2 + 4] = u32x4{ad[2], sg[2], ad[3], sg[3]};
-      }
+      for (int q = 0; q < 4; ++q) wd[q] = (base + (ebuf[h][q] >> 1) * (uint32_t)(TL * SZ)) | (ebuf[h][q] << 31);
+      *(u32x4*)&ents[qb] = wd;
     }
     bnd = bnd_nx;
     bndN = bndN_nx;
@@ -168,17 +141,9 @@ __global__ void __launch_bounds__(NW * 64)
       load_meta(t + 1);
       load_tile(t + 1, b ^ 1);
     }
-    if (active) {
-      if constexpr (!PACK)
-        gather_chunk_lds_ms<T, NJ, RPL, VT, MS>(ents_of(b), (t - blk) * pass.kcap, bnd, bndN, lane_part,
-                                                b ? zaddr1 : zaddr0, acc);
-      else if constexpr (RPL == 1)
-        gather_chunk_e32<T, NJ, MS>(ents_of(b), (t - blk) * pass.kcap, bnd, bndN, lane_part, b ? zaddr1 : zaddr0,
-                                    acc);
-      else
-        gather_chunk_e32_rpl<T, NJ, RPL, VT, MS>(ents_of(b), (t - blk) * pass.kcap, bnd, bndN, lane_part,
-                                                 b ? zaddr1 : zaddr0, acc);
-    }
+    if (active)
+      gather_chunk_lds_win<T, NJ, RPL, VT, (NJ < 4 ? NJ : 4), true, false, MS>(
+          ents_of(b), (t - blk) * pass.kcap, bnd, bndN, lane_part, b ? zaddr1 : zaddr0, acc);
   }
 
   if (!active) return;
@@ -388,7 +353,7 @@ int launch_sjlt_dma_t(Ctx* c, int dtype, int nw, int nj, int kc, const void* A, 
 }
 
 size_t dma_lds_bytes(int esz, int kc, int tl, int nblk, int kcap) {
-  return 2 * (size_t)(kc + 1) * tl * esz + 2 * ((size_t)nblk * kcap + 8) * (esz == 8 ? 4 : 8);
+  return 2 * (size_t)(kc + 1) * tl * esz + 2 * ((size_t)nblk * kcap + 8) * 4;
 }
 
 template <typename T, int NW, int NJ, int RPL, int KCK>
